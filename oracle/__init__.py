@@ -1,0 +1,17 @@
+"""FP64 CPU oracle of the split-step Fourier propagation.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+its Python binding) imports, links or calls this package; only the test
+suite, the smoke check and the CPU-baseline leg of the benchmark do.  It
+shares no code, tables or constants with the GPU path.
+"""
+
+from .ssfm_ref import (si_params, angular_frequency, linear_factor,
+                       nl_step_length, linear_step, nl_step, ase_words,
+                       uniform_from_words, ase_noise, edfa, propagate,
+                       propagate_batch)
+
+__all__ = ["si_params", "angular_frequency", "linear_factor",
+           "nl_step_length", "linear_step", "nl_step", "ase_words",
+           "uniform_from_words", "ase_noise", "edfa", "propagate",
+           "propagate_batch"]
