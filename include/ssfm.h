@@ -1,0 +1,154 @@
+/*
+ * ssfm.h -- C ABI of the MI355X split-step Fourier (SSFM) propagation library.
+ *
+ * The library propagates sampled optical fields through amplified fibre
+ * links.  Per polarisation p the field A_p(z, T) obeys
+ *
+ *   dA_p/dz = -(alpha/2) A_p - i (beta2/2) d^2A_p/dT^2
+ *             + i c_nl gamma (sum_q |A_q|^2) A_p
+ *
+ * (the nonlinear Schroedinger equation with loss, Agrawal, "Nonlinear Fiber
+ * Optics", ch. 2; with two polarisations and c_nl = 8/9 it is the Manakov-PMD
+ * equation of Marcuse, Menyuk and Wai, J. Lightwave Technol. 15(9), 1997).
+ * The paper accompanying this library does not state a propagation model;
+ * the equation, scheme and amplifier model are the textbook ones above.
+ *
+ * Scheme: symmetric split-step Fourier method with merged half steps.  A
+ * span of n steps of length h = span/n is
+ *   L(h/2) . [N(h) . L(h)]^(n-1) . N(h) . L(h/2) . EDFA
+ * with L(x) the exact linear (dispersion + loss) solution over length x,
+ * applied in the frequency domain, and N(h) the exact nonlinear phase
+ * rotation with the loss-weighted length h_nl = 2 sinh(alpha h/2)/alpha.
+ * The amplifier multiplies the field by sqrt(G) and, when enabled, adds
+ * amplified spontaneous emission: a white circular complex Gaussian of
+ * variance n_sp (G-1) h_planck nu fs per polarisation (n_sp = NF/2).
+ *
+ * Noise draws (bitwise contract): Philox4x64-10 (Salmon et al., SC'11) with
+ * key (seed, realization * 2^16 + span) and counter (t, 0, 0, 0) for time
+ * sample t; words (w0, w1) serve polarisation x and (w2, w3) polarisation
+ * y; u = ((w >> 41) + 1/2) 2^-23; Box-Muller g = sqrt(-2 ln u1) e^{2 pi i u2};
+ * noise = sqrt(variance / 2) * g.
+ *
+ * Field layout: complex64 interleaved (re, im) in device memory, shape
+ * [batch][n_pol][n_samples], each polarisation contiguous, natural time
+ * order.  All entry points return an int status (0 = success, negative =
+ * error); nothing is thrown across the ABI.  On error, ssfm_last_error()
+ * returns a thread-local message describing it.
+ */
+#ifndef SSFM_H_
+#define SSFM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSFM_OK 0
+#define SSFM_EINVAL (-1)       /* an argument is out of range or malformed    */
+#define SSFM_ENOMEM (-2)       /* a device or host allocation failed          */
+#define SSFM_EHIP (-3)         /* a HIP runtime call or kernel launch failed  */
+#define SSFM_EUNSUPPORTED (-4) /* valid request this build does not implement */
+
+/* One amplified fibre link, in the units such links are quoted in.
+ * Every span is identical.  The library converts to SI internally:
+ * alpha[1/m] = alpha_db_per_km * ln(10)/10 / 1e3 (power attenuation),
+ * beta2[s^2/m] = beta2_ps2_per_km * 1e-27, gamma[1/(W m)] = gamma_per_w_km
+ * * 1e-3, h = span_km * 1e3 / steps_per_span. */
+typedef struct ssfm_link {
+  int32_t n_pol;             /* 1 = scalar NLSE, 2 = Manakov                  */
+  int32_t n_spans;           /* >= 1, < 65536                                 */
+  int32_t steps_per_span;    /* >= 1                                          */
+  int32_t ase;               /* 0 = noiseless amplifier, 1 = add ASE (G > 1)  */
+  int64_t n_samples;         /* per polarisation; power of two, 2^6 .. 2^20   */
+  double sample_rate_hz;     /* fs > 0; sample spacing 1/fs                   */
+  double span_km;            /* > 0                                           */
+  double alpha_db_per_km;    /* any finite value (negative = gain)            */
+  double beta2_ps2_per_km;   /* any finite value                              */
+  double gamma_per_w_km;     /* any finite value                              */
+  double nl_factor;          /* c_nl; NaN selects 1 (n_pol 1) or 8/9 (n_pol 2) */
+  double edfa_gain_db;       /* power gain per span end; 0 dB = unity gain    */
+  double edfa_nf_db;         /* noise figure, used when ase = 1               */
+  double carrier_hz;         /* optical carrier; NaN selects 193.4145 THz     */
+  uint32_t flags;            /* reserved, must be 0                           */
+  uint32_t reserved;         /* must be 0                                     */
+} ssfm_link;
+
+/* Opaque plan: device tables (dispersion operator, twiddles) for one link on
+ * one device.  Immutable after creation, so one plan may serve concurrent
+ * calls on several streams of its device. */
+typedef struct ssfm_plan_s* ssfm_plan_t;
+
+/* Plan description, for callers that report what will run. */
+typedef struct ssfm_plan_info {
+  int32_t path;              /* 1 = LDS-resident field, 2 = four-step passes  */
+  int32_t n1;                /* four-step: column FFT length (0 for path 1)   */
+  int32_t n2;                /* four-step: row FFT length (0 for path 1)      */
+  int32_t columns_per_tile;  /* four-step: column-tile width at batch >= 8    */
+  int64_t launches_per_call; /* kernel launches of one ssfm_forward call      */
+  int64_t table_bytes;       /* device memory owned by the plan               */
+} ssfm_plan_info;
+
+/* Build a plan for `link` on HIP device `hip_device`.
+ * On success *out receives a plan that the caller releases with
+ * ssfm_plan_destroy.  Errors: SSFM_EINVAL for an invalid link or NULL out
+ * (no device work is done), SSFM_ENOMEM if the tables cannot be allocated,
+ * SSFM_EHIP if the device cannot be selected.  Blocks until the tables are
+ * on the device. */
+int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out);
+
+/* Release a plan and its device memory.  NULL is accepted.  The caller must
+ * ensure no call using the plan is still running on any stream. */
+int ssfm_plan_destroy(ssfm_plan_t plan);
+
+/* Fill *info for `plan`.  SSFM_EINVAL if either pointer is NULL. */
+int ssfm_plan_get_info(ssfm_plan_t plan, ssfm_plan_info* info);
+
+/* Propagate `batch` independent fields through the whole link, in place.
+ *   field:  device pointer to complex64 [batch][n_pol][n_samples], 8-byte
+ *           aligned, owned by the caller; overwritten with the output.
+ *   batch:  >= 1.  Realisation r of the batch draws its noise with key
+ *           (seed, r * 2^16 + span).
+ *   stream: hipStream_t to order the work on (NULL = default stream).
+ * Asynchronous with respect to the host: returns once the kernels are
+ * enqueued; a fault inside a kernel surfaces at the caller's next
+ * synchronisation.  Errors: SSFM_EINVAL (NULL plan/field, misaligned field,
+ * batch < 1), SSFM_EHIP (launch failure). */
+int ssfm_forward(ssfm_plan_t plan, void* field, int64_t batch, uint64_t seed,
+                 void* stream);
+
+/* As ssfm_forward, restricted to spans [span_begin, span_end) and with the
+ * noise realisation index of batch entry b equal to realization0 + b.  A run
+ * split into consecutive span ranges gives the same result, bit for bit, as
+ * one call over the union (span-granular checkpoint and resume).
+ * SSFM_EINVAL unless 0 <= span_begin <= span_end <= n_spans. */
+int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
+                       uint64_t seed, uint64_t realization0, int32_t span_begin,
+                       int32_t span_end, void* stream);
+
+/* Adjoint (reverse-mode) propagation for gradients through the link.
+ * Not implemented in this build: returns SSFM_EUNSUPPORTED after argument
+ * validation. */
+int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
+                 int64_t batch, uint64_t seed, void* stream);
+
+/* Independent realisations of different lengths, launch powers and span
+ * counts in one call.  Not implemented in this build: returns
+ * SSFM_EUNSUPPORTED after argument validation. */
+int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
+               const uint64_t* seeds, int hip_device, void* stream);
+
+/* Static description of a status code (never NULL). */
+const char* ssfm_status_string(int status);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* ssfm_last_error(void);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int ssfm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSFM_H_ */

@@ -1,0 +1,278 @@
+// Register/LDS Stockham FFT for gfx950, FP64 arithmetic.
+//
+// Layout contract.  A length-M transform is carried by T = M/16 lanes; lane j
+// holds the 16 elements j + T*r (r = 0..15) of its transform in registers, in
+// both the input and the output order (the Stockham autosort keeps natural
+// order).  Between radix passes the elements go through LDS; element i of a
+// transform lives at lds[i * ls] (ls = element stride, so several transforms
+// can be interleaved column-wise for conflict-free access).
+//
+// Pass structure (self-sorting Stockham, decimation in time): with Ns the
+// product of the radices already applied, butterfly jj reads elements
+// jj + r*M/R, multiplies element r by W_{Ns*R}^{(jj mod Ns) r}, applies a
+// radix-R DFT and writes element r to (jj / Ns) * Ns * R + (jj mod Ns) + r*Ns.
+// Radices are 16 repeated, then one of 8/4/2 for the remainder.  A lane runs
+// 16/R butterflies per pass: jj = j + T*q, q = 0..16/R-1, whose element r is
+// register q + r*16/R -- which is why the first pass can read the registers
+// and the last pass can leave its output there.
+//
+// Twiddles come from a table tw[m] = exp(-2 pi i m / M), m in [0, M), built in
+// FP64 on the host; the inverse transform uses their conjugates.  All
+// arithmetic is FP64, so the coefficients of the linear operator carry no
+// FP32 rounding (a fixed rounding error in them would repeat identically at
+// every split step and grow linearly with the step count).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssfm {
+
+struct cd {
+  double re, im;
+};
+
+__device__ __forceinline__ cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd operator-(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
+// a * b
+__device__ __forceinline__ cd cmul(cd a, cd b) {
+  return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+// a * conj(b)
+__device__ __forceinline__ cd cmulc(cd a, cd b) {
+  return {fma(a.re, b.re, a.im * b.im), fma(a.im, b.re, -a.re * b.im)};
+}
+template <bool CONJ>
+__device__ __forceinline__ cd cmul_t(cd a, cd b) {
+  return CONJ ? cmulc(a, b) : cmul(a, b);
+}
+// multiply by -i (forward) or +i (inverse): the exp(-+ i pi/2) rotation
+template <bool INV>
+__device__ __forceinline__ cd rot90(cd a) {
+  return INV ? cd{-a.im, a.re} : cd{a.im, -a.re};
+}
+
+// exp(-2 pi i k / 16) for the forward transform, conjugate for the inverse.
+template <bool INV, int K>
+__device__ __forceinline__ cd w16() {
+  constexpr double c1 = 0.92387953251128675613;  // cos(pi/8)
+  constexpr double s1 = 0.38268343236508977173;  // sin(pi/8)
+  constexpr double r2 = 0.70710678118654752440;  // cos(pi/4)
+  constexpr int k = K & 15;
+  constexpr double re = k == 0 ? 1.0 : k == 1 ? c1 : k == 2 ? r2 : k == 3 ? s1
+                      : k == 4 ? 0.0 : k == 5 ? -s1 : k == 6 ? -r2 : k == 7 ? -c1
+                      : k == 8 ? -1.0 : k == 9 ? -c1 : k == 10 ? -r2 : k == 11 ? -s1
+                      : k == 12 ? 0.0 : k == 13 ? s1 : k == 14 ? r2 : c1;
+  constexpr double sn = k == 0 ? 0.0 : k == 1 ? s1 : k == 2 ? r2 : k == 3 ? c1
+                      : k == 4 ? 1.0 : k == 5 ? c1 : k == 6 ? r2 : k == 7 ? s1
+                      : k == 8 ? 0.0 : k == 9 ? -s1 : k == 10 ? -r2 : k == 11 ? -c1
+                      : k == 12 ? -1.0 : k == 13 ? -c1 : k == 14 ? -r2 : -s1;
+  return {re, INV ? sn : -sn};
+}
+
+template <bool INV, int K>
+__device__ __forceinline__ cd mul_w16(cd a) {
+  if constexpr ((K & 15) == 0) return a;
+  else if constexpr ((K & 15) == 4) return rot90<INV>(a);
+  else if constexpr ((K & 15) == 8) return cd{-a.re, -a.im};
+  else if constexpr ((K & 15) == 12) return rot90<!INV>(a);
+  else return cmul(a, w16<INV, K>());
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(cd& a0, cd& a1) {
+  cd t = a0;
+  a0 = t + a1;
+  a1 = t - a1;
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(cd& a0, cd& a1, cd& a2, cd& a3) {
+  cd t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<INV>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+// In-place DFT of length R on v[0..R-1], natural order in and out.
+// R = 8 and 16 use the 4 x 2 and 4 x 4 Cooley-Tukey splits with the
+// internal twiddles W_R^{b c}.
+template <int R, bool INV>
+__device__ __forceinline__ void dft(cd* v) {
+  if constexpr (R == 2) {
+    dft2<INV>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    // n = 2a + b, k = c + 4d
+    dft4<INV>(v[0], v[2], v[4], v[6]);  // b = 0 -> Y0[c] at 2c
+    dft4<INV>(v[1], v[3], v[5], v[7]);  // b = 1 -> Y1[c] at 2c+1
+    v[3] = mul_w16<INV, 2>(v[3]);       // W8^1 = W16^2
+    v[5] = mul_w16<INV, 4>(v[5]);       // W8^2
+    v[7] = mul_w16<INV, 6>(v[7]);       // W8^3
+    cd x[8];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      cd a = v[2 * c], b = v[2 * c + 1];
+      dft2<INV>(a, b);
+      x[c] = a;
+      x[c + 4] = b;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = x[i];
+  } else {
+    static_assert(R == 16, "radix");
+    // n = 4a + b, k = c + 4d
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dft4<INV>(v[b], v[4 + b], v[8 + b], v[12 + b]);
+    // element 4c + b now holds Y_b[c]; apply W16^{b c}
+    v[5] = mul_w16<INV, 1>(v[5]);
+    v[6] = mul_w16<INV, 2>(v[6]);
+    v[7] = mul_w16<INV, 3>(v[7]);
+    v[9] = mul_w16<INV, 2>(v[9]);
+    v[10] = mul_w16<INV, 4>(v[10]);
+    v[11] = mul_w16<INV, 6>(v[11]);
+    v[13] = mul_w16<INV, 3>(v[13]);
+    v[14] = mul_w16<INV, 6>(v[14]);
+    v[15] = mul_w16<INV, 9>(v[15]);
+    cd x[16];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      cd a0 = v[4 * c], a1 = v[4 * c + 1], a2 = v[4 * c + 2], a3 = v[4 * c + 3];
+      dft4<INV>(a0, a1, a2, a3);
+      x[c] = a0;
+      x[c + 4] = a1;
+      x[c + 8] = a2;
+      x[c + 12] = a3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = x[i];
+  }
+}
+
+// Radix of pass p for a length-M transform: 16, ..., 16, then M / 16^k.
+template <int M>
+struct fft_shape {
+  static constexpr int log2m = M == 64 ? 6 : M == 128 ? 7 : M == 256 ? 8 : M == 512 ? 9
+                             : M == 1024 ? 10 : M == 2048 ? 11 : M == 4096 ? 12
+                             : M == 8192 ? 13 : M == 16384 ? 14 : -1;
+  static_assert(log2m > 0, "unsupported transform length");
+  static constexpr int n16 = log2m / 4;
+  static constexpr int rest = 1 << (log2m % 4);
+  static constexpr int passes = n16 + (rest > 1 ? 1 : 0);
+  static constexpr int T = M / 16;
+  static constexpr int radix(int p) { return p < n16 ? 16 : rest; }
+  static constexpr int ns(int p) {  // product of radices before pass p
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= radix(i);
+    return s;
+  }
+};
+
+// LDS element conversions: FP64 values are held as cd or rounded to float2.
+__device__ __forceinline__ void lds_put(cd* p, cd v) { *p = v; }
+__device__ __forceinline__ void lds_put(float2* p, cd v) {
+  *p = make_float2((float)v.re, (float)v.im);
+}
+__device__ __forceinline__ cd lds_get(const cd* p) { return *p; }
+__device__ __forceinline__ cd lds_get(const float2* p) {
+  float2 v = *p;
+  return {(double)v.x, (double)v.y};
+}
+
+// Read the inputs of pass P from LDS into the registers.
+template <int M, int P, typename L>
+__device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, int j) {
+  using S = fft_shape<M>;
+  constexpr int R = S::radix(P);
+  constexpr int NB = 16 / R;
+  constexpr int T = S::T;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int jj = j + T * q;
+#pragma unroll
+    for (int r = 0; r < R; ++r) reg[q + r * NB] = lds_get(lds + (jj + r * (M / R)) * ls);
+  }
+}
+
+// Twiddle, butterfly and write of pass P.  DST_REG: the outputs stay in the
+// registers (last pass), otherwise they are written to LDS.
+template <int M, int P, bool INV, bool DST_REG, typename L>
+__device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int j,
+                                             const cd* __restrict__ tw) {
+  using S = fft_shape<M>;
+  constexpr int R = S::radix(P);
+  constexpr int NS = S::ns(P);
+  constexpr int NB = 16 / R;
+  constexpr int T = S::T;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int jj = j + T * q;
+    cd v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = reg[q + r * NB];
+    if constexpr (NS > 1) {
+      const int k = jj % NS;
+      constexpr int step = M / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul_t<INV>(v[r], tw[k * r * step]);
+    }
+    dft<R, INV>(v);
+    if constexpr (DST_REG) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) reg[q + r * NB] = v[r];
+    } else {
+      const int base = (jj / NS) * NS * R + (jj % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds_put(lds + (base + r * NS) * ls, v[r]);
+    }
+  }
+}
+
+template <int M, bool INV, int P, int NT, typename L>
+__device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride, int ls,
+                                         int j, const cd* __restrict__ tw) {
+  using S = fft_shape<M>;
+  if constexpr (P < S::passes) {
+    constexpr bool last = P == S::passes - 1;
+    __syncthreads();  // writes of the previous pass are visible
+#pragma unroll
+    for (int t = 0; t < NT; ++t) pass_load<M, P>(reg[t], lds + t * tstride, ls, j);
+    if constexpr (!last) __syncthreads();  // all reads done before overwriting
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      pass_compute<M, P, INV, last>(reg[t], lds + t * tstride, ls, j, tw);
+    fft_rest<M, INV, P + 1, NT>(reg, lds, tstride, ls, j, tw);
+  }
+}
+
+// NT unnormalised transforms of length M advanced in lockstep (they share the
+// barriers); transform t uses the LDS region starting at lds + t * tstride.
+// Lane j holds elements j + (M/16) r of each transform on entry and on exit.
+// Forward uses exp(-2 pi i nk/M), inverse exp(+2 pi i nk/M).
+// Contains block-wide barriers: every lane of the block must call it.
+template <int M, bool INV, int NT, typename L>
+__device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride, int ls,
+                                          int j, const cd* __restrict__ tw) {
+  using S = fft_shape<M>;
+  if constexpr (S::passes == 1) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) pass_compute<M, 0, INV, true>(reg[t], lds, ls, j, tw);
+  } else {
+    __syncthreads();  // earlier readers of the LDS regions are done
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      pass_compute<M, 0, INV, false>(reg[t], lds + t * tstride, ls, j, tw);
+    fft_rest<M, INV, 1, NT>(reg, lds, tstride, ls, j, tw);
+  }
+}
+
+template <int M, bool INV, typename L>
+__device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
+                                    const cd* __restrict__ tw) {
+  fft_multi<M, INV, 1>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);
+}
+
+}  // namespace ssfm

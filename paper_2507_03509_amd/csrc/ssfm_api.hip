@@ -1,0 +1,398 @@
+// Host side of libssfm: link validation, FP64 operator tables, launch
+// orchestration and the C ABI declared in include/ssfm.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "ssfm.h"
+#include "ssfm_internal.hpp"
+
+using ssfm::cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  return fail(SSFM_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+constexpr double kPlanck = 6.62607015e-34;      // J s
+constexpr double kDefaultCarrier = 193.4145e12;  // Hz (1550 nm)
+constexpr double kPi = 3.14159265358979323846;
+
+bool finite(double v) { return isfinite(v) != 0; }
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t status = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    status = hipGetDevice(&prev);
+    if (status == hipSuccess && prev != dev) status = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct ssfm_plan_s {
+  ssfm_link link{};
+  int device = 0;
+  ssfm::KernelSet ks;
+  int n_pol = 1;
+  int64_t n = 0;
+  int steps = 0, spans = 0;
+  double gspan = 1.0, sigma_h = 0.0;
+  std::vector<double> kappa;
+  // device tables
+  cd* h_half = nullptr;
+  cd* h_full = nullptr;
+  cd* tw_n = nullptr;  // path 1: W_N
+  cd* tw1 = nullptr;   // path 2: W_N1
+  cd* tw2 = nullptr;   // path 2: W_N2
+  cd* twA = nullptr;   // path 2: W_N^{a N2}
+  cd* twB = nullptr;   // path 2: W_N^{b}
+  double* d_kappa = nullptr;
+  size_t table_bytes = 0;
+  std::vector<void*> allocations;
+
+  ~ssfm_plan_s() {
+    for (void* p : allocations) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+int validate_link(const ssfm_link* l) {
+  if (!l) return fail(SSFM_EINVAL, "link is NULL");
+  if (l->n_pol != 1 && l->n_pol != 2) return fail(SSFM_EINVAL, "n_pol must be 1 or 2, got %d", l->n_pol);
+  const int64_t n = l->n_samples;
+  if (n < 64 || n > (int64_t(1) << 18) || (n & (n - 1)) != 0)
+    return fail(SSFM_EINVAL, "n_samples must be a power of two in [2^6, 2^18], got %lld",
+                (long long)n);
+  if (l->n_spans < 1 || l->n_spans > 65535)
+    return fail(SSFM_EINVAL, "n_spans must be in [1, 65535], got %d", l->n_spans);
+  if (l->steps_per_span < 1 || l->steps_per_span > (1 << 24))
+    return fail(SSFM_EINVAL, "steps_per_span must be in [1, 2^24], got %d", l->steps_per_span);
+  if (l->ase != 0 && l->ase != 1) return fail(SSFM_EINVAL, "ase must be 0 or 1");
+  if (!finite(l->sample_rate_hz) || l->sample_rate_hz <= 0)
+    return fail(SSFM_EINVAL, "sample_rate_hz must be finite and > 0");
+  if (!finite(l->span_km) || l->span_km <= 0) return fail(SSFM_EINVAL, "span_km must be finite and > 0");
+  if (!finite(l->alpha_db_per_km) || !finite(l->beta2_ps2_per_km) || !finite(l->gamma_per_w_km))
+    return fail(SSFM_EINVAL, "alpha, beta2 and gamma must be finite");
+  if (!finite(l->nl_factor) && !isnan(l->nl_factor))
+    return fail(SSFM_EINVAL, "nl_factor must be finite or NaN");
+  if (!finite(l->edfa_gain_db)) return fail(SSFM_EINVAL, "edfa_gain_db must be finite");
+  if (l->ase && !finite(l->edfa_nf_db)) return fail(SSFM_EINVAL, "edfa_nf_db must be finite");
+  if (!isnan(l->carrier_hz) && (!finite(l->carrier_hz) || l->carrier_hz <= 0))
+    return fail(SSFM_EINVAL, "carrier_hz must be NaN or finite and > 0");
+  if (l->flags != 0 || l->reserved != 0) return fail(SSFM_EINVAL, "flags and reserved must be 0");
+  return SSFM_OK;
+}
+
+// W_M^m = exp(-2 pi i m / M) for m < count.
+std::vector<cd> twiddles(int64_t M, int64_t count, int64_t stride) {
+  std::vector<cd> t((size_t)count);
+  for (int64_t m = 0; m < count; ++m) {
+    const double ang = -2.0 * kPi * (double)((m * stride) % M) / (double)M;
+    t[(size_t)m] = {cos(ang), sin(ang)};
+  }
+  return t;
+}
+
+template <typename T>
+int upload(ssfm_plan_s* p, T** dst, const std::vector<T>& src) {
+  const size_t bytes = src.size() * sizeof(T);
+  void* d = nullptr;
+  if (getenv("SSFM_FAIL_ALLOC") && strcmp(getenv("SSFM_FAIL_ALLOC"), "1") == 0)
+    return fail(SSFM_ENOMEM, "allocation failure injected by SSFM_FAIL_ALLOC=1");
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return fail(SSFM_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  p->allocations.push_back(d);
+  e = hipMemcpy(d, src.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpy (plan tables)");
+  *dst = static_cast<T*>(d);
+  p->table_bytes += bytes;
+  return SSFM_OK;
+}
+
+int build_tables(ssfm_plan_s* p) {
+  const ssfm_link& l = p->link;
+  const int64_t n = p->n;
+  const double fs = l.sample_rate_hz;
+  const double alpha = l.alpha_db_per_km * log(10.0) / 10.0 / 1e3;  // 1/m, power
+  const double beta2 = l.beta2_ps2_per_km * 1e-27;                   // s^2/m
+  const double gamma = l.gamma_per_w_km * 1e-3;                      // 1/(W m)
+  const double c_nl = isnan(l.nl_factor) ? (l.n_pol == 1 ? 1.0 : 8.0 / 9.0) : l.nl_factor;
+  const double span_m = l.span_km * 1e3;
+  const double h = span_m / l.steps_per_span;
+  const double h_nl = alpha == 0.0 ? h : 2.0 * sinh(alpha * h / 2.0) / alpha;
+  const double gain = pow(10.0, l.edfa_gain_db / 10.0);
+  const double carrier = isnan(l.carrier_hz) ? kDefaultCarrier : l.carrier_hz;
+
+  p->kappa.resize((size_t)p->steps);
+  for (int j = 0; j < p->steps; ++j)
+    p->kappa[(size_t)j] = c_nl * gamma * h_nl * exp(-alpha * (j + 0.5) * h);
+  p->gspan = sqrt(gain) * exp(-alpha * span_m / 2.0);
+  p->sigma_h = 0.0;
+  if (l.ase && gain > 1.0) {
+    const double nf = pow(10.0, l.edfa_nf_db / 10.0);
+    const double var = (nf / 2.0) * (gain - 1.0) * kPlanck * carrier * fs;  // per pol
+    p->sigma_h = sqrt(var / 2.0);
+  }
+
+  // dispersion operator, 1/N of the unnormalised inverse FFT folded in
+  auto omega = [&](int64_t k) {
+    const int64_t kk = k < (n + 1) / 2 ? k : k - n;  // fftfreq order
+    return 2.0 * kPi * (double)kk * fs / (double)n;
+  };
+  std::vector<cd> hh((size_t)n), hf((size_t)n);
+  const int n1 = p->ks.n1, n2 = p->ks.n2;
+  for (int64_t k = 0; k < n; ++k) {
+    const double w = omega(k);
+    const double th_full = 0.5 * beta2 * w * w * h;
+    const double th_half = 0.5 * th_full;
+    // storage position: natural order (path 1) or [k1][k2] with k = k1 + N1 k2
+    const int64_t pos = p->ks.path == 1 ? k : (k % n1) * n2 + k / n1;
+    hh[(size_t)pos] = {cos(th_half) / (double)n, sin(th_half) / (double)n};
+    hf[(size_t)pos] = {cos(th_full) / (double)n, sin(th_full) / (double)n};
+  }
+  int rc;
+  if ((rc = upload(p, &p->h_half, hh)) != SSFM_OK) return rc;
+  if ((rc = upload(p, &p->h_full, hf)) != SSFM_OK) return rc;
+  if ((rc = upload(p, &p->d_kappa, p->kappa)) != SSFM_OK) return rc;
+  if (p->ks.path == 1) {
+    if ((rc = upload(p, &p->tw_n, twiddles(n, n, 1))) != SSFM_OK) return rc;
+  } else {
+    if ((rc = upload(p, &p->tw1, twiddles(n1, n1, 1))) != SSFM_OK) return rc;
+    if ((rc = upload(p, &p->tw2, twiddles(n2, n2, 1))) != SSFM_OK) return rc;
+    if ((rc = upload(p, &p->twA, twiddles(n, n1, n2))) != SSFM_OK) return rc;
+    if ((rc = upload(p, &p->twB, twiddles(n, n2, 1))) != SSFM_OK) return rc;
+  }
+  return SSFM_OK;
+}
+
+int64_t launches_per_call(const ssfm_plan_s* p) {
+  if (p->ks.path == 1) return 1;
+  return 1 + (int64_t)p->spans * (p->steps + 1) * 2;
+}
+
+// Wide tiles once a batch offers at least two workgroups per compute unit.
+bool use_wide(const ssfm_plan_s* p, int64_t batch) {
+  const int64_t wide_blocks = batch * (p->ks.n2 / p->ks.wide.columns);
+  return wide_blocks >= 512;
+}
+
+int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uint64_t real0,
+                int s0, int s1, hipStream_t st) {
+  const ssfm::KernelSet& ks = p->ks;
+  hipError_t e;
+  if (s0 == s1) return SSFM_OK;
+  if (ks.path == 1) {
+    ssfm::LdsArgs a{};
+    a.field = field;
+    a.h_half = p->h_half;
+    a.h_full = p->h_full;
+    a.tw = p->tw_n;
+    a.kappa = p->d_kappa;
+    a.steps = p->steps;
+    a.span_begin = s0;
+    a.span_end = s1;
+    a.gspan = p->gspan;
+    a.sigma_h = p->sigma_h;
+    a.seed = seed;
+    a.realization0 = real0;
+    if ((e = ks.lds(a, batch, st)) != hipSuccess) return fail_hip(e, "k1_lds launch");
+    return SSFM_OK;
+  }
+  const bool wide = use_wide(p, batch);
+  const ssfm::FourStepKernels& cols = wide ? ks.wide : ks.narrow;
+  const ssfm::RowLaunch row = wide ? ks.row_wide : ks.row_narrow;
+  const int64_t rows = batch * p->n_pol * ks.n1;
+  ssfm::ColArgs a{};
+  a.field = field;
+  a.tw1 = p->tw1;
+  a.twA = p->twA;
+  a.twB = p->twB;
+  a.n2 = ks.n2;
+  a.log2_n2 = 0;
+  while ((1 << a.log2_n2) < ks.n2) ++a.log2_n2;
+  a.n = p->n;
+  a.gspan = p->gspan;
+  a.sigma_h = p->sigma_h;
+  a.seed = seed;
+  a.realization0 = real0;
+  if ((e = cols.col[ssfm::MODE_FIRST](a, batch, st)) != hipSuccess) return fail_hip(e, "k3 launch");
+  for (int s = s0; s < s1; ++s) {
+    a.span = s;
+    for (int i = 0; i <= p->steps; ++i) {
+      const cd* H = (i == 0 || i == p->steps) ? p->h_half : p->h_full;
+      if ((e = row(field, H, p->tw2, ks.n1, rows, st)) != hipSuccess) return fail_hip(e, "k2 launch");
+      int mode;
+      if (i < p->steps) {
+        mode = ssfm::MODE_NL;
+        a.kappa = p->kappa[(size_t)i];
+      } else {
+        mode = s + 1 < s1 ? ssfm::MODE_EDFA : ssfm::MODE_LAST;
+      }
+      if ((e = cols.col[mode](a, batch, st)) != hipSuccess) return fail_hip(e, "k3 launch");
+    }
+  }
+  return SSFM_OK;
+}
+
+int check_call(ssfm_plan_t plan, const void* field, int64_t batch) {
+  if (!plan) return fail(SSFM_EINVAL, "plan is NULL");
+  if (!field) return fail(SSFM_EINVAL, "field is NULL");
+  if (((uintptr_t)field & 7u) != 0) return fail(SSFM_EINVAL, "field must be 8-byte aligned");
+  if (batch < 1) return fail(SSFM_EINVAL, "batch must be >= 1, got %lld", (long long)batch);
+  const int64_t n2 = plan->ks.path == 2 ? plan->ks.n2 : 1;
+  const int64_t cols = plan->ks.path == 2 ? plan->ks.narrow.columns : 1;
+  if (batch * (n2 / cols) > 0x7fffffff || batch * plan->n_pol * plan->ks.n1 > (int64_t(1) << 40))
+    return fail(SSFM_EINVAL, "batch %lld exceeds the launch grid", (long long)batch);
+  return SSFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out) {
+  g_last_error.clear();
+  if (!out) return fail(SSFM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_link(link);
+  if (rc != SSFM_OK) return rc;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceCount");
+  if (hip_device < 0 || hip_device >= count)
+    return fail(SSFM_EINVAL, "hip_device %d out of range (%d devices)", hip_device, count);
+  DeviceGuard guard(hip_device);
+  if (guard.status != hipSuccess) return fail_hip(guard.status, "hipSetDevice");
+
+  ssfm_plan_s* p = new (std::nothrow) ssfm_plan_s();
+  if (!p) return fail(SSFM_ENOMEM, "host allocation of the plan failed");
+  p->link = *link;
+  p->device = hip_device;
+  p->n_pol = link->n_pol;
+  p->n = link->n_samples;
+  p->steps = link->steps_per_span;
+  p->spans = link->n_spans;
+  if (!ssfm::select_kernels(p->n, p->n_pol, p->ks)) {
+    delete p;
+    return fail(SSFM_EUNSUPPORTED, "no kernel for n_samples = %lld", (long long)link->n_samples);
+  }
+  if (p->ks.prepare != hipSuccess) {
+    const hipError_t pe = p->ks.prepare;
+    delete p;
+    return fail_hip(pe, "hipFuncSetAttribute (LDS size)");
+  }
+  rc = build_tables(p);
+  if (rc != SSFM_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return SSFM_OK;
+}
+
+int ssfm_plan_destroy(ssfm_plan_t plan) {
+  if (!plan) return SSFM_OK;
+  DeviceGuard guard(plan->device);
+  delete plan;
+  return SSFM_OK;
+}
+
+int ssfm_plan_get_info(ssfm_plan_t plan, ssfm_plan_info* info) {
+  if (!plan || !info) return fail(SSFM_EINVAL, "plan and info must be non-NULL");
+  info->path = plan->ks.path;
+  info->n1 = plan->ks.path == 2 ? plan->ks.n1 : 0;
+  info->n2 = plan->ks.path == 2 ? plan->ks.n2 : 0;
+  info->columns_per_tile = plan->ks.path == 2 ? plan->ks.wide.columns : 0;
+  info->launches_per_call = launches_per_call(plan);
+  info->table_bytes = (int64_t)plan->table_bytes;
+  return SSFM_OK;
+}
+
+int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch, uint64_t seed,
+                       uint64_t realization0, int32_t span_begin, int32_t span_end,
+                       void* stream) {
+  g_last_error.clear();
+  int rc = check_call(plan, field, batch);
+  if (rc != SSFM_OK) return rc;
+  if (span_begin < 0 || span_end < span_begin || span_end > plan->spans)
+    return fail(SSFM_EINVAL, "span range [%d, %d) outside [0, %d]", span_begin, span_end,
+                plan->spans);
+  DeviceGuard guard(plan->device);
+  if (guard.status != hipSuccess) return fail_hip(guard.status, "hipSetDevice");
+  return run_forward(plan, static_cast<float2*>(field), batch, seed, realization0, span_begin,
+                     span_end, static_cast<hipStream_t>(stream));
+}
+
+int ssfm_forward(ssfm_plan_t plan, void* field, int64_t batch, uint64_t seed, void* stream) {
+  if (!plan) return fail(SSFM_EINVAL, "plan is NULL");
+  return ssfm_forward_spans(plan, field, batch, seed, 0, 0, plan->spans, stream);
+}
+
+int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t batch,
+                 uint64_t seed, void* stream) {
+  (void)seed;
+  (void)stream;
+  g_last_error.clear();
+  int rc = check_call(plan, field_in, batch);
+  if (rc != SSFM_OK) return rc;
+  if (!grad) return fail(SSFM_EINVAL, "grad is NULL");
+  return fail(SSFM_EUNSUPPORTED, "ssfm_adjoint is not implemented in this build");
+}
+
+int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
+               const uint64_t* seeds, int hip_device, void* stream) {
+  (void)hip_device;
+  (void)stream;
+  g_last_error.clear();
+  if (!links || !fields || !seeds) return fail(SSFM_EINVAL, "links, fields and seeds must be non-NULL");
+  if (count < 1) return fail(SSFM_EINVAL, "count must be >= 1");
+  for (int64_t i = 0; i < count; ++i) {
+    int rc = validate_link(&links[i]);
+    if (rc != SSFM_OK) return rc;
+    if (!fields[i]) return fail(SSFM_EINVAL, "fields[%lld] is NULL", (long long)i);
+  }
+  return fail(SSFM_EUNSUPPORTED, "ssfm_batch is not implemented in this build");
+}
+
+const char* ssfm_status_string(int status) {
+  switch (status) {
+    case SSFM_OK: return "success";
+    case SSFM_EINVAL: return "invalid argument";
+    case SSFM_ENOMEM: return "out of memory";
+    case SSFM_EHIP: return "HIP runtime error";
+    case SSFM_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* ssfm_last_error(void) { return g_last_error.c_str(); }
+
+int ssfm_version(void) { return 100; }
+
+}  // extern "C"

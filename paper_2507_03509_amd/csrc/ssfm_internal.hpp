@@ -1,0 +1,71 @@
+// Types shared by the kernel and host translation units of libssfm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_dev.hpp"
+
+namespace ssfm {
+
+// column-pass variants
+enum { MODE_FIRST = 0,   // time -> mixed domain (start of the link)
+       MODE_NL = 1,      // mixed -> time, nonlinear phase, time -> mixed
+       MODE_EDFA = 2,    // mixed -> time, amplifier + ASE, time -> mixed
+       MODE_LAST = 3 };  // mixed -> time, amplifier + ASE (end of the link)
+
+struct ColArgs {
+  float2* field;
+  const cd* tw1;     // W_N1^m, m < N1
+  const cd* twA;     // W_N^{a N2}, a < N1
+  const cd* twB;     // W_N^{b}, b < N2
+  int n2;
+  int log2_n2;
+  int64_t n;         // N = N1 * N2 samples per polarisation
+  double kappa;      // nonlinear coefficient of this step (MODE_NL)
+  double gspan;      // field factor at the span end (MODE_EDFA, MODE_LAST)
+  double sigma_h;    // ASE standard deviation per quadrature, 0 = none
+  uint64_t seed;
+  uint64_t realization0;
+  int span;
+};
+
+struct LdsArgs {
+  float2* field;
+  const cd* h_half;  // exp(i (beta2/2) omega^2 h/2) / N, natural bin order
+  const cd* h_full;  // exp(i (beta2/2) omega^2 h) / N
+  const cd* tw;      // W_N^m, m < N
+  const double* kappa;
+  int steps;
+  int span_begin, span_end;
+  double gspan;
+  double sigma_h;
+  uint64_t seed;
+  uint64_t realization0;
+};
+
+using RowLaunch = hipError_t (*)(float2*, const cd*, const cd*, int, int64_t, hipStream_t);
+using ColLaunch = hipError_t (*)(const ColArgs&, int64_t, hipStream_t);
+using LdsLaunch = hipError_t (*)(const LdsArgs&, int64_t, hipStream_t);
+
+struct FourStepKernels {
+  ColLaunch col[4] = {nullptr, nullptr, nullptr, nullptr};
+  int columns = 0;
+  hipError_t prepare_status = hipSuccess;
+};
+
+struct KernelSet {
+  int path = 0;  // 1 = LDS-resident, 2 = four-step
+  int n1 = 0, n2 = 0;
+  LdsLaunch lds = nullptr;
+  RowLaunch row_wide = nullptr, row_narrow = nullptr;
+  int rows_wide = 0, rows_narrow = 0;  // rows per workgroup
+  FourStepKernels wide, narrow;
+  hipError_t prepare = hipSuccess;
+};
+
+// Pick the kernel instantiations for n samples per polarisation.  Returns
+// false if no instantiation exists for that size.
+bool select_kernels(int64_t n, int n_pol, KernelSet& ks);
+
+}  // namespace ssfm

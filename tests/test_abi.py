@@ -1,0 +1,107 @@
+"""The C-ABI library: it loads, exports what include/ssfm.h declares, and
+rejects invalid arguments before touching a device (runs without a GPU)."""
+
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssfm.h")
+
+ssfm = pytest.importorskip("paper_2507_03509_amd")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(ssfm.library_path()),
+                                reason="libssfm.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(ssfm_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for need in ("ssfm_plan", "ssfm_forward", "ssfm_adjoint", "ssfm_batch",
+                 "ssfm_plan_destroy", "ssfm_status_string"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ssfm.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layout_matches_header():
+    # ssfm_link: 4 int32, int64, 9 doubles, 2 uint32 = 16 + 8 + 72 + 8
+    import ctypes
+    assert ctypes.sizeof(ssfm.SsfmLink) == 104
+    assert ssfm.SsfmLink.n_samples.offset == 16
+    assert ctypes.sizeof(ssfm.SsfmPlanInfo) == 32
+
+
+def test_status_strings_and_version():
+    assert ssfm.ssfm_status_string(0) == "success"
+    assert ssfm.ssfm_status_string(-1) == "invalid argument"
+    assert ssfm.ssfm_status_string(-4) == "unsupported"
+    assert ssfm.ssfm_status_string(12345) == "unknown status"
+    assert ssfm.ssfm_version() >= 100
+
+
+def _good(**kw):
+    base = dict(n_pol=2, n_spans=1, steps_per_span=10, ase=1, n_samples=4096,
+                sample_rate_hz=128e9, span_km=80.0, alpha_db_per_km=0.2,
+                beta2_ps2_per_km=-21.7, gamma_per_w_km=1.3, nl_factor=math.nan,
+                edfa_gain_db=16.0, edfa_nf_db=5.0, carrier_hz=math.nan, flags=0,
+                reserved=0)
+    base.update(kw)
+    return ssfm.SsfmLink(**base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_pol=3), dict(n_pol=0), dict(n_samples=1000), dict(n_samples=32),
+    dict(n_samples=1 << 19), dict(n_spans=0), dict(n_spans=70000),
+    dict(steps_per_span=0), dict(ase=2), dict(sample_rate_hz=0.0),
+    dict(sample_rate_hz=math.inf), dict(span_km=-1.0), dict(alpha_db_per_km=math.nan),
+    dict(beta2_ps2_per_km=math.inf), dict(gamma_per_w_km=math.nan),
+    dict(nl_factor=math.inf), dict(edfa_gain_db=math.nan), dict(edfa_nf_db=math.nan),
+    dict(carrier_hz=-1.0), dict(flags=1), dict(reserved=3),
+])
+def test_invalid_links_are_rejected_without_a_device(bad):
+    with pytest.raises(ssfm.SsfmError) as e:
+        ssfm.ssfm_plan(_good(**bad), 0)
+    assert e.value.status == ssfm.SSFM_EINVAL
+    assert ssfm.ssfm_last_error()
+
+
+def test_null_arguments_are_rejected():
+    import ctypes
+    lib = ssfm.load_library()
+    assert lib.ssfm_plan(None, 0, None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_forward(None, None, 1, 0, None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_forward_spans(None, None, 1, 0, 0, 0, 1, None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_plan_get_info(None, None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_adjoint(None, None, None, 1, 0, None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_batch(None, None, 0, None, 0, None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_plan_destroy(None) == ssfm.SSFM_OK
+    out = ctypes.c_void_p()
+    link = _good()
+    # valid link but NULL output pointer
+    assert lib.ssfm_plan(ctypes.byref(link), 0, None) == ssfm.SSFM_EINVAL
+
+
+def test_batch_entry_validates_each_link():
+    import ctypes
+    lib = ssfm.load_library()
+    links = (ssfm.SsfmLink * 2)(_good(), _good(n_pol=5))
+    ptrs = (ctypes.c_void_p * 2)(8, 16)
+    seeds = (ctypes.c_uint64 * 2)(1, 2)
+    assert lib.ssfm_batch(links, ptrs, 2, seeds, 0, None) == ssfm.SSFM_EINVAL
+
+
+def test_binding_rejects_non_tensor_fields():
+    with pytest.raises(TypeError):
+        ssfm._field_args([1, 2, 3])
