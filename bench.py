@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput of the split-step Fourier path on one MI355X.
+
+A step is one ssfm_forward call: every realisation of the batch propagated
+through the whole link (all spans and split steps).  The default workload is
+the dual-polarisation Manakov link of 10 x 80 km SSMF spans, 100 steps per
+span, EDFA 16 dB / NF 5 dB with ASE, 2^16 samples per polarisation, for a
+batch of independent realisations (distinct noise keys, 16 distinct symbol
+streams tiled over the batch); the field is resident in HBM before timing.
+
+Metric: sample-steps/s = batch * n_samples * (spans * steps_per_span) / time.
+One JSON line on stdout.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Manakov SSFM sample-steps/s and fwd+adjoint time at ≤1e-5 rel. field error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--single-steps", type=int, default=3,
+                    help="timed calls of the batch-1 figure (0 to skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def traffic_record(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2507_03509_amd", "csrc", "ssfm_kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    ent = rec.get(kernel)
+    if not ent or ent.get("kernel_source_sha256") != digest:
+        return None
+    return ent
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the SSFM "
+              "path has no multi-GPU code", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2507_03509_amd as ssfm
+    from workloads import CONFIGS, make_field
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    ssfm.load_library()  # raises if the HIP library is not built
+    w = CONFIGS[args.workload]
+    link = w.link
+    n, p = link.n_samples, link.n_pol
+    total_steps = link.n_spans * link.steps_per_span
+    batch = args.batch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # ---- inputs: resident in HBM before timing -------------------------------
+    distinct = min(batch, 16)
+    host = np.stack([make_field(w, seed=w.symbol_seed + i) for i in range(distinct)])
+    base = torch.from_numpy(host.astype(np.complex64)).to(dev)
+    reps = (batch + distinct - 1) // distinct
+    field = base.repeat(reps, 1, 1)[:batch].contiguous()
+    ref_in = host[0].copy()
+    plan = ssfm.Plan(link, device=0)
+    info = plan.info
+    stream = torch.cuda.current_stream(dev)
+    log(f"workload {w.name} batch={batch} plan={info}")
+
+    # ---- first call doubles as the parity sample (realisation 0) ------------
+    plan.forward(field, seed=w.ase_seed, stream=stream)
+    torch.cuda.synchronize()
+    gpu_out0 = field[0].cpu().numpy().astype(np.complex128)
+    for _ in range(max(0, args.warmup - 1)):
+        plan.forward(field, seed=w.ase_seed, stream=stream)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K calls, per-launch HIP events on the same stream ----
+    ssfm.ssfm_profile_begin(plan.handle)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(args.steps):
+        plan.forward(field, seed=w.ase_seed, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    stats = ssfm.ssfm_profile_end(plan.handle)
+    ms_total = t0.elapsed_time(t1)
+    ms_per_step = ms_total / args.steps
+    value = batch * n * total_steps / (ms_per_step / 1e3)
+    log(f"timed {args.steps} calls: {ms_per_step:.3f} ms/call, wall {wall:.3f}s, "
+        f"{value:.4e} sample-steps/s")
+    for s in stats:
+        log(f"  {s['name']}: {s['launches']} launches, {s['total_ms']:.3f} ms, "
+            f"{s['field_bytes'] / (s['total_ms'] * 1e-3) / 1e9:.1f} GB/s algorithmic")
+
+    dom = max(stats, key=lambda s: s["total_ms"])
+    per_launch_ms = dom["total_ms"] / dom["launches"]
+    bytes_per_launch = dom["field_bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+    tr = traffic_record(dom["name"])
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": tr["bytes_per_launch"] if tr else None,
+        "kernel": dom["name"], "avg_launch_us": round(per_launch_ms * 1e3, 3),
+        "algorithmic_bytes_per_launch": bytes_per_launch,
+        "kernels": {s["name"]: {"launches": s["launches"],
+                                "avg_us": round(s["total_ms"] / s["launches"] * 1e3, 3),
+                                "gbs": round(s["field_bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1)}
+                    for s in stats},
+    }
+
+    # ---- one field (batch 1): the latency-bound figure ----------------------
+    single = None
+    if args.single_steps > 0 and batch > 1:
+        f1 = field[:1].clone()
+        plan.forward(f1, seed=w.ase_seed, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.single_steps):
+            plan.forward(f1, seed=w.ase_seed, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1) / args.single_steps
+        single = {"ms_per_call": round(ms1, 3),
+                  "us_per_split_step": round(ms1 * 1e3 / total_steps, 3),
+                  "sample_steps_per_s": n * total_steps / (ms1 / 1e3)}
+        log(f"batch 1: {ms1:.3f} ms/call, {single['sample_steps_per_s']:.4e} sample-steps/s")
+
+    # ---- CPU oracle on one realisation (also the parity reference) ----------
+    cpu = None
+    rel_err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        c0 = time.perf_counter()
+        want = oracle.propagate(ref_in, link, seed=w.ase_seed, realization=0)
+        csec = time.perf_counter() - c0
+        rel_err = float(np.linalg.norm(gpu_out0 - want) / np.linalg.norm(want))
+        cpu = {"value": n * total_steps / csec, "unit": "sample-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"1 realisation of the same link ({link.n_spans} spans x "
+                         f"{link.steps_per_span} steps, {n} samples x {p} pol), FP64 NumPy, "
+                         f"{csec:.1f} s on {cpu_model()} ({os.cpu_count()} logical CPUs, "
+                         "single-threaded FFT and elementwise ops)"}
+        log(f"oracle: {csec:.1f} s, rel err of GPU realisation 0 = {rel_err:.3e}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "sample-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name} x{batch} realisations",
+                   "n_samples": n, "n_pol": p, "spans": link.n_spans,
+                   "steps_per_span": link.steps_per_span, "batch": batch,
+                   "field_storage": "complex64", "linear_step_arithmetic": "f64",
+                   "parallelism": "single-gpu"},
+        "rel_err_vs_oracle": rel_err,
+        "fwd_adjoint_ms": None,
+        "batch1": single,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -60,7 +60,7 @@ typedef struct ssfm_link {
   int32_t n_spans;           /* >= 1, < 65536                                 */
   int32_t steps_per_span;    /* >= 1                                          */
   int32_t ase;               /* 0 = noiseless amplifier, 1 = add ASE (G > 1)  */
-  int64_t n_samples;         /* per polarisation; power of two, 2^6 .. 2^20   */
+  int64_t n_samples;         /* per polarisation; power of two, 2^6 .. 2^18   */
   double sample_rate_hz;     /* fs > 0; sample spacing 1/fs                   */
   double span_km;            /* > 0                                           */
   double alpha_db_per_km;    /* any finite value (negative = gain)            */
@@ -137,6 +137,26 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
  * SSFM_EUNSUPPORTED after argument validation. */
 int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
                const uint64_t* seeds, int hip_device, void* stream);
+
+/* Per-kernel timing, for reporting achieved bandwidth.  Between
+ * ssfm_profile_begin and ssfm_profile_end every kernel launch of this plan
+ * is bracketed by two HIP events recorded on the launch's own stream; the
+ * GPU time between them is summed per kernel family.  Not thread-safe: one
+ * profiling window per plan at a time. */
+typedef struct ssfm_kernel_stats {
+  char name[24];      /* "k1_lds", "k2_rows" or "k3_cols"                    */
+  int64_t launches;   /* launches recorded in the window                     */
+  double total_ms;    /* sum of per-launch GPU durations                     */
+  double field_bytes; /* algorithmic HBM bytes: field read + write, summed   */
+} ssfm_kernel_stats;
+
+/* Start recording (clears earlier records).  SSFM_EINVAL on NULL plan. */
+int ssfm_profile_begin(ssfm_plan_t plan);
+
+/* Wait for the recorded events, stop recording and write up to `capacity`
+ * entries (one per kernel family that ran) to `out`; *count receives the
+ * number written.  SSFM_EINVAL on NULL arguments, SSFM_EHIP on event errors. */
+int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int* count);
 
 /* Static description of a status code (never NULL). */
 const char* ssfm_status_string(int status);

@@ -22,6 +22,7 @@ __all__ = [
     "make_link", "ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info",
     "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch",
     "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
+    "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats",
     "SSFM_OK", "SSFM_EINVAL", "SSFM_ENOMEM", "SSFM_EHIP", "SSFM_EUNSUPPORTED",
 ]
 
@@ -77,6 +78,17 @@ class SsfmPlanInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class SsfmKernelStats(ctypes.Structure):
+    """Mirror of ``ssfm_kernel_stats``."""
+
+    _fields_ = [
+        ("name", ctypes.c_char * 24),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("field_bytes", ctypes.c_double),
+    ]
+
+
 class SsfmError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         self.status = status
@@ -107,16 +119,34 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_adjoint.argtypes = [P, VP, VP, I64, U64, VP]
     lib.ssfm_batch.argtypes = [ctypes.POINTER(SsfmLink), ctypes.POINTER(ctypes.c_void_p), I64,
                                ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, VP]
+    lib.ssfm_profile_begin.argtypes = [P]
+    lib.ssfm_profile_end.argtypes = [P, ctypes.POINTER(SsfmKernelStats), ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int)]
     lib.ssfm_status_string.argtypes = [ctypes.c_int]
     lib.ssfm_status_string.restype = ctypes.c_char_p
     lib.ssfm_last_error.argtypes = []
     lib.ssfm_last_error.restype = ctypes.c_char_p
     lib.ssfm_version.argtypes = []
     for name in ("ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info", "ssfm_forward",
-                 "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version"):
+                 "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version",
+                 "ssfm_profile_begin", "ssfm_profile_end"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def ssfm_profile_begin(plan: int) -> None:
+    _check(load_library().ssfm_profile_begin(plan), "ssfm_profile_begin")
+
+
+def ssfm_profile_end(plan: int) -> list:
+    """Per-kernel-family stats of the window: list of dicts."""
+    out = (SsfmKernelStats * 8)()
+    cnt = ctypes.c_int(0)
+    _check(load_library().ssfm_profile_end(plan, out, 8, ctypes.byref(cnt)), "ssfm_profile_end")
+    return [dict(name=out[i].name.decode(), launches=out[i].launches,
+                 total_ms=out[i].total_ms, field_bytes=out[i].field_bytes)
+            for i in range(cnt.value)]
 
 
 def ssfm_status_string(status: int) -> str:

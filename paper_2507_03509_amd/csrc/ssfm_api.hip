@@ -74,8 +74,15 @@ struct ssfm_plan_s {
   double* d_kappa = nullptr;
   size_t table_bytes = 0;
   std::vector<void*> allocations;
+  // profiling window: event pairs around each launch
+  bool profiling = false;
+  std::vector<hipEvent_t> events;  // pool, reused across windows
+  size_t events_used = 0;
+  std::vector<int> prof_kind;
+  std::vector<double> prof_bytes;
 
   ~ssfm_plan_s() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
     for (void* p : allocations) (void)hipFree(p);
   }
 };
@@ -191,6 +198,37 @@ int build_tables(ssfm_plan_s* p) {
   return SSFM_OK;
 }
 
+enum { KIND_LDS = 0, KIND_ROW = 1, KIND_COL = 2, KIND_COUNT = 3 };
+const char* const kKindName[KIND_COUNT] = {"k1_lds", "k2_rows", "k3_cols"};
+
+hipError_t next_event(ssfm_plan_s* p, hipEvent_t* ev) {
+  if (p->events_used == p->events.size()) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    p->events.push_back(e);
+  }
+  *ev = p->events[p->events_used++];
+  return hipSuccess;
+}
+
+// Launch through `fn`, bracketed by events when the plan is profiling.
+template <typename F>
+hipError_t launch(ssfm_plan_s* p, int kind, double bytes, hipStream_t st, F&& fn) {
+  if (!p->profiling) return fn();
+  hipEvent_t a, b;
+  hipError_t e = next_event(p, &a);
+  if (e == hipSuccess) e = next_event(p, &b);
+  if (e == hipSuccess) e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  e = fn();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, st);
+  p->prof_kind.push_back(kind);
+  p->prof_bytes.push_back(bytes);
+  return e;
+}
+
 int64_t launches_per_call(const ssfm_plan_s* p) {
   if (p->ks.path == 1) return 1;
   return 1 + (int64_t)p->spans * (p->steps + 1) * 2;
@@ -207,6 +245,8 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
   const ssfm::KernelSet& ks = p->ks;
   hipError_t e;
   if (s0 == s1) return SSFM_OK;
+  // algorithmic HBM traffic of one launch: the field read once and written once
+  const double field_bytes = 2.0 * (double)batch * p->n_pol * (double)p->n * sizeof(float2);
   if (ks.path == 1) {
     ssfm::LdsArgs a{};
     a.field = field;
@@ -221,7 +261,8 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
     a.sigma_h = p->sigma_h;
     a.seed = seed;
     a.realization0 = real0;
-    if ((e = ks.lds(a, batch, st)) != hipSuccess) return fail_hip(e, "k1_lds launch");
+    if ((e = launch(p, KIND_LDS, field_bytes, st, [&] { return ks.lds(a, batch, st); })) != hipSuccess)
+      return fail_hip(e, "k1_lds launch");
     return SSFM_OK;
   }
   const bool wide = use_wide(p, batch);
@@ -241,12 +282,16 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
   a.sigma_h = p->sigma_h;
   a.seed = seed;
   a.realization0 = real0;
-  if ((e = cols.col[ssfm::MODE_FIRST](a, batch, st)) != hipSuccess) return fail_hip(e, "k3 launch");
+  if ((e = launch(p, KIND_COL, field_bytes, st,
+                  [&] { return cols.col[ssfm::MODE_FIRST](a, batch, st); })) != hipSuccess)
+    return fail_hip(e, "k3 launch");
   for (int s = s0; s < s1; ++s) {
     a.span = s;
     for (int i = 0; i <= p->steps; ++i) {
       const cd* H = (i == 0 || i == p->steps) ? p->h_half : p->h_full;
-      if ((e = row(field, H, p->tw2, ks.n1, rows, st)) != hipSuccess) return fail_hip(e, "k2 launch");
+      if ((e = launch(p, KIND_ROW, field_bytes, st,
+                      [&] { return row(field, H, p->tw2, ks.n1, rows, st); })) != hipSuccess)
+        return fail_hip(e, "k2 launch");
       int mode;
       if (i < p->steps) {
         mode = ssfm::MODE_NL;
@@ -254,7 +299,9 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
       } else {
         mode = s + 1 < s1 ? ssfm::MODE_EDFA : ssfm::MODE_LAST;
       }
-      if ((e = cols.col[mode](a, batch, st)) != hipSuccess) return fail_hip(e, "k3 launch");
+      if ((e = launch(p, KIND_COL, field_bytes, st,
+                      [&] { return cols.col[mode](a, batch, st); })) != hipSuccess)
+        return fail_hip(e, "k3 launch");
     }
   }
   return SSFM_OK;
@@ -378,6 +425,52 @@ int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
     if (!fields[i]) return fail(SSFM_EINVAL, "fields[%lld] is NULL", (long long)i);
   }
   return fail(SSFM_EUNSUPPORTED, "ssfm_batch is not implemented in this build");
+}
+
+int ssfm_profile_begin(ssfm_plan_t plan) {
+  if (!plan) return fail(SSFM_EINVAL, "plan is NULL");
+  plan->profiling = true;
+  plan->events_used = 0;
+  plan->prof_kind.clear();
+  plan->prof_bytes.clear();
+  return SSFM_OK;
+}
+
+int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int* count) {
+  if (!plan || !out || !count) return fail(SSFM_EINVAL, "plan, out and count must be non-NULL");
+  plan->profiling = false;
+  DeviceGuard guard(plan->device);
+  double ms[KIND_COUNT] = {0, 0, 0}, bytes[KIND_COUNT] = {0, 0, 0};
+  int64_t n[KIND_COUNT] = {0, 0, 0};
+  const size_t launches = plan->prof_kind.size();
+  if (launches) {
+    hipError_t e = hipEventSynchronize(plan->events[2 * launches - 1]);
+    if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+  }
+  for (size_t i = 0; i < launches; ++i) {
+    float t = 0.0f;
+    hipError_t e = hipEventElapsedTime(&t, plan->events[2 * i], plan->events[2 * i + 1]);
+    if (e != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
+    const int k = plan->prof_kind[i];
+    ms[k] += t;
+    bytes[k] += plan->prof_bytes[i];
+    n[k] += 1;
+  }
+  int w = 0;
+  for (int k = 0; k < KIND_COUNT && w < capacity; ++k) {
+    if (!n[k]) continue;
+    memset(&out[w], 0, sizeof out[w]);
+    snprintf(out[w].name, sizeof out[w].name, "%s", kKindName[k]);
+    out[w].launches = n[k];
+    out[w].total_ms = ms[k];
+    out[w].field_bytes = bytes[k];
+    ++w;
+  }
+  *count = w;
+  plan->events_used = 0;
+  plan->prof_kind.clear();
+  plan->prof_bytes.clear();
+  return SSFM_OK;
 }
 
 const char* ssfm_status_string(int status) {

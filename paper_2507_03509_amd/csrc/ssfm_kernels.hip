@@ -37,6 +37,11 @@ __device__ __forceinline__ cd load_c64(const float2* p) {
 __device__ __forceinline__ void store_c64(float2* p, cd v) {
   *p = make_float2((float)v.re, (float)v.im);
 }
+// The state at a span boundary is the complex64 field: rounding to it there
+// makes a run split at span boundaries identical, bit for bit, to one call.
+__device__ __forceinline__ cd round_c64(cd v) {
+  return {(double)(float)v.re, (double)(float)v.im};
+}
 
 // exp(i phi) with phi given in FP64: FP32 sine/cosine, then one Newton step
 // on the modulus in FP64 so the rotation is unit-modulus to ~1e-15 (a rotation
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
           v.re = fma(a.sigma_h, (double)g.x, v.re);
           v.im = fma(a.sigma_h, (double)g.y, v.im);
         }
-        reg[r] = v;
+        reg[r] = round_c64(v);
       }
     }
   }
@@ -235,6 +240,7 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
           reg[q][r].re = fma(a.sigma_h, (double)g.x, reg[q][r].re);
           reg[q][r].im = fma(a.sigma_h, (double)g.y, reg[q][r].im);
         }
+        reg[q][r] = round_c64(reg[q][r]);
       }
     }
   }
