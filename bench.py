@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--single-steps", type=int, default=3,
                     help="timed calls of the batch-1 figure (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a "
+                         "known-size reference for hardware traffic counters)")
     return ap.parse_args()
 
 
@@ -98,6 +101,16 @@ def main() -> int:
     batch = args.batch
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read + {nbytes} bytes written")
+        del src, dst
 
     # ---- inputs: resident in HBM before timing -------------------------------
     distinct = min(batch, 16)

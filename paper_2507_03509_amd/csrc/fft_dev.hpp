@@ -16,8 +16,10 @@
 // register q + r*16/R -- which is why the first pass can read the registers
 // and the last pass can leave its output there.
 //
-// Twiddles come from a table tw[m] = exp(-2 pi i m / M), m in [0, M), built in
-// FP64 on the host; the inverse transform uses their conjugates.  All
+// Twiddles come from a table built in FP64 on the host: for each pass p >= 1
+// a block of ns(p) rows of radix(p) entries, row k holding
+// W_{ns R}^{k r} = exp(-2 pi i k r / (ns R)); the inverse transform uses their
+// conjugates.  All
 // arithmetic is FP64, so the coefficients of the linear operator carry no
 // FP32 rounding (a fixed rounding error in them would repeat identically at
 // every split step and grow linearly with the step count).
@@ -152,23 +154,37 @@ __device__ __forceinline__ void dft(cd* v) {
   }
 }
 
-// Radix of pass p for a length-M transform: 16, ..., 16, then M / 16^k.
+// Pass structure of a length-2^log2m transform: radix 16 repeated, then the
+// remainder 2^(log2m mod 4).  Host (twiddle tables) and device share these.
+__host__ __device__ constexpr int fft_passes(int log2m) {
+  return log2m / 4 + (log2m % 4 ? 1 : 0);
+}
+__host__ __device__ constexpr int fft_radix(int log2m, int p) {
+  return p < log2m / 4 ? 16 : 1 << (log2m % 4);
+}
+__host__ __device__ constexpr int fft_ns(int log2m, int p) {  // product of radices before pass p
+  int s = 1;
+  for (int i = 0; i < p; ++i) s *= fft_radix(log2m, i);
+  return s;
+}
+// pass p >= 1 reads its twiddle rows [ns(p)][radix(p)] starting here
+__host__ __device__ constexpr int fft_tw_offset(int log2m, int p) {
+  int o = 0;
+  for (int i = 1; i < p; ++i) o += fft_ns(log2m, i) * fft_radix(log2m, i);
+  return o;
+}
+
 template <int M>
 struct fft_shape {
   static constexpr int log2m = M == 64 ? 6 : M == 128 ? 7 : M == 256 ? 8 : M == 512 ? 9
                              : M == 1024 ? 10 : M == 2048 ? 11 : M == 4096 ? 12
                              : M == 8192 ? 13 : M == 16384 ? 14 : -1;
   static_assert(log2m > 0, "unsupported transform length");
-  static constexpr int n16 = log2m / 4;
-  static constexpr int rest = 1 << (log2m % 4);
-  static constexpr int passes = n16 + (rest > 1 ? 1 : 0);
+  static constexpr int passes = fft_passes(log2m);
   static constexpr int T = M / 16;
-  static constexpr int radix(int p) { return p < n16 ? 16 : rest; }
-  static constexpr int ns(int p) {  // product of radices before pass p
-    int s = 1;
-    for (int i = 0; i < p; ++i) s *= radix(i);
-    return s;
-  }
+  static constexpr int radix(int p) { return fft_radix(log2m, p); }
+  static constexpr int ns(int p) { return fft_ns(log2m, p); }
+  static constexpr int tw_offset(int p) { return fft_tw_offset(log2m, p); }
 };
 
 // LDS element conversions: FP64 values are held as cd or rounded to float2.
@@ -182,8 +198,16 @@ __device__ __forceinline__ cd lds_get(const float2* p) {
   return {(double)v.x, (double)v.y};
 }
 
+// LDS slot of element i.  Contiguous transforms (ls = 1) get one pad slot per
+// 16 elements: the first pass writes with a stride of 16 elements, which
+// would otherwise put every lane of a row on the same bank.
+template <bool PAD>
+__device__ __forceinline__ int lds_slot(int i, int ls) {
+  return PAD ? i + (i >> 4) : i * ls;
+}
+
 // Read the inputs of pass P from LDS into the registers.
-template <int M, int P, typename L>
+template <int M, int P, bool PAD, typename L>
 __device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, int j) {
   using S = fft_shape<M>;
   constexpr int R = S::radix(P);
@@ -193,13 +217,13 @@ __device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, i
   for (int q = 0; q < NB; ++q) {
     const int jj = j + T * q;
 #pragma unroll
-    for (int r = 0; r < R; ++r) reg[q + r * NB] = lds_get(lds + (jj + r * (M / R)) * ls);
+    for (int r = 0; r < R; ++r) reg[q + r * NB] = lds_get(lds + lds_slot<PAD>(jj + r * (M / R), ls));
   }
 }
 
 // Twiddle, butterfly and write of pass P.  DST_REG: the outputs stay in the
 // registers (last pass), otherwise they are written to LDS.
-template <int M, int P, bool INV, bool DST_REG, typename L>
+template <int M, int P, bool INV, bool DST_REG, bool PAD, typename L>
 __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int j,
                                              const cd* __restrict__ tw) {
   using S = fft_shape<M>;
@@ -214,10 +238,18 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = reg[q + r * NB];
     if constexpr (NS > 1) {
-      const int k = jj % NS;
-      constexpr int step = M / (NS * R);
+      // W_{NS R}^{k r}, r = 1..R-1: w = W_{NS R}^k from this pass's table
+      // block (row k, entry 1), powers by FP64 products (~r ulps of FP64, far
+      // below the single-precision storage of the field; one load per
+      // butterfly keeps the register footprint down)
+      const cd* t = tw + S::tw_offset(P) + (jj % NS) * R;
+      const cd w = t[1];
+      cd wr = w;
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul_t<INV>(v[r], tw[k * r * step]);
+      for (int r = 1; r < R; ++r) {
+        v[r] = cmul_t<INV>(v[r], wr);
+        if (r + 1 < R) wr = cmul(wr, w);
+      }
     }
     dft<R, INV>(v);
     if constexpr (DST_REG) {
@@ -226,12 +258,12 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
     } else {
       const int base = (jj / NS) * NS * R + (jj % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds_put(lds + (base + r * NS) * ls, v[r]);
+      for (int r = 0; r < R; ++r) lds_put(lds + lds_slot<PAD>(base + r * NS, ls), v[r]);
     }
   }
 }
 
-template <int M, bool INV, int P, int NT, typename L>
+template <int M, bool INV, int P, int NT, bool PAD, typename L>
 __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride, int ls,
                                          int j, const cd* __restrict__ tw) {
   using S = fft_shape<M>;
@@ -239,12 +271,12 @@ __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride,
     constexpr bool last = P == S::passes - 1;
     __syncthreads();  // writes of the previous pass are visible
 #pragma unroll
-    for (int t = 0; t < NT; ++t) pass_load<M, P>(reg[t], lds + t * tstride, ls, j);
+    for (int t = 0; t < NT; ++t) pass_load<M, P, PAD>(reg[t], lds + t * tstride, ls, j);
     if constexpr (!last) __syncthreads();  // all reads done before overwriting
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-      pass_compute<M, P, INV, last>(reg[t], lds + t * tstride, ls, j, tw);
-    fft_rest<M, INV, P + 1, NT>(reg, lds, tstride, ls, j, tw);
+      pass_compute<M, P, INV, last, PAD>(reg[t], lds + t * tstride, ls, j, tw);
+    fft_rest<M, INV, P + 1, NT, PAD>(reg, lds, tstride, ls, j, tw);
   }
 }
 
@@ -253,26 +285,28 @@ __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride,
 // Lane j holds elements j + (M/16) r of each transform on entry and on exit.
 // Forward uses exp(-2 pi i nk/M), inverse exp(+2 pi i nk/M).
 // Contains block-wide barriers: every lane of the block must call it.
-template <int M, bool INV, int NT, typename L>
+// PAD selects the padded slot map for contiguous transforms (ls = 1); a
+// padded transform occupies M + M/16 slots.
+template <int M, bool INV, int NT, bool PAD, typename L>
 __device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride, int ls,
                                           int j, const cd* __restrict__ tw) {
   using S = fft_shape<M>;
   if constexpr (S::passes == 1) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) pass_compute<M, 0, INV, true>(reg[t], lds, ls, j, tw);
+    for (int t = 0; t < NT; ++t) pass_compute<M, 0, INV, true, PAD>(reg[t], lds, ls, j, tw);
   } else {
     __syncthreads();  // earlier readers of the LDS regions are done
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-      pass_compute<M, 0, INV, false>(reg[t], lds + t * tstride, ls, j, tw);
-    fft_rest<M, INV, 1, NT>(reg, lds, tstride, ls, j, tw);
+      pass_compute<M, 0, INV, false, PAD>(reg[t], lds + t * tstride, ls, j, tw);
+    fft_rest<M, INV, 1, NT, PAD>(reg, lds, tstride, ls, j, tw);
   }
 }
 
-template <int M, bool INV, typename L>
+template <int M, bool INV, bool PAD, typename L>
 __device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
                                     const cd* __restrict__ tw) {
-  fft_multi<M, INV, 1>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);
+  fft_multi<M, INV, 1, PAD>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);
 }
 
 }  // namespace ssfm

@@ -116,6 +116,26 @@ int validate_link(const ssfm_link* l) {
   return SSFM_OK;
 }
 
+// Stockham pass twiddles of a length-M transform: for each pass p >= 1, rows
+// k < ns(p) of radix(p) entries W_{ns R}^{k r} (the layout the kernels read).
+std::vector<cd> pass_twiddles(int M) {
+  int l = 0;
+  while ((1 << l) < M) ++l;
+  const int passes = ssfm::fft_passes(l);
+  std::vector<cd> t((size_t)ssfm::fft_tw_offset(l, passes));
+  for (int p = 1; p < passes; ++p) {
+    const int ns = ssfm::fft_ns(l, p), R = ssfm::fft_radix(l, p);
+    const int base = ssfm::fft_tw_offset(l, p);
+    for (int k = 0; k < ns; ++k)
+      for (int r = 0; r < R; ++r) {
+        const double ang = -2.0 * kPi * (double)((k * r) % (ns * R)) / (double)(ns * R);
+        t[(size_t)(base + k * R + r)] = {cos(ang), sin(ang)};
+      }
+  }
+  if (t.empty()) t.push_back({1.0, 0.0});
+  return t;
+}
+
 // W_M^m = exp(-2 pi i m / M) for m < count.
 std::vector<cd> twiddles(int64_t M, int64_t count, int64_t stride) {
   std::vector<cd> t((size_t)count);
@@ -188,10 +208,10 @@ int build_tables(ssfm_plan_s* p) {
   if ((rc = upload(p, &p->h_full, hf)) != SSFM_OK) return rc;
   if ((rc = upload(p, &p->d_kappa, p->kappa)) != SSFM_OK) return rc;
   if (p->ks.path == 1) {
-    if ((rc = upload(p, &p->tw_n, twiddles(n, n, 1))) != SSFM_OK) return rc;
+    if ((rc = upload(p, &p->tw_n, pass_twiddles((int)n))) != SSFM_OK) return rc;
   } else {
-    if ((rc = upload(p, &p->tw1, twiddles(n1, n1, 1))) != SSFM_OK) return rc;
-    if ((rc = upload(p, &p->tw2, twiddles(n2, n2, 1))) != SSFM_OK) return rc;
+    if ((rc = upload(p, &p->tw1, pass_twiddles(n1))) != SSFM_OK) return rc;
+    if ((rc = upload(p, &p->tw2, pass_twiddles(n2))) != SSFM_OK) return rc;
     if ((rc = upload(p, &p->twA, twiddles(n, n1, n2))) != SSFM_OK) return rc;
     if ((rc = upload(p, &p->twB, twiddles(n, n2, 1))) != SSFM_OK) return rc;
   }
@@ -234,10 +254,21 @@ int64_t launches_per_call(const ssfm_plan_s* p) {
   return 1 + (int64_t)p->spans * (p->steps + 1) * 2;
 }
 
-// Wide tiles once a batch offers at least two workgroups per compute unit.
-bool use_wide(const ssfm_plan_s* p, int64_t batch) {
-  const int64_t wide_blocks = batch * (p->ks.n2 / p->ks.wide.columns);
-  return wide_blocks >= 512;
+// Column tiles: wide once a batch offers at least two workgroups per compute
+// unit, otherwise narrow.  SSFM_COLUMNS (a tile width among the compiled
+// ones) overrides the choice, for tuning.
+const ssfm::FourStepKernels& pick_cols(const ssfm_plan_s* p, int64_t batch, bool* wide) {
+  const char* env = getenv("SSFM_COLUMNS");
+  if (env) {
+    const int c = atoi(env);
+    for (const ssfm::FourStepKernels* k : {&p->ks.wide, &p->ks.mid, &p->ks.narrow})
+      if (k->columns == c) {
+        *wide = k != &p->ks.narrow;
+        return *k;
+      }
+  }
+  *wide = batch * (p->ks.n2 / p->ks.wide.columns) >= 512;
+  return *wide ? p->ks.wide : p->ks.narrow;
 }
 
 int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uint64_t real0,
@@ -265,18 +296,23 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
       return fail_hip(e, "k1_lds launch");
     return SSFM_OK;
   }
-  const bool wide = use_wide(p, batch);
-  const ssfm::FourStepKernels& cols = wide ? ks.wide : ks.narrow;
+  bool wide = false;
+  const ssfm::FourStepKernels& cols = pick_cols(p, batch, &wide);
   const ssfm::RowLaunch row = wide ? ks.row_wide : ks.row_narrow;
   const int64_t rows = batch * p->n_pol * ks.n1;
+  int log2_n2 = 0;
+  while ((1 << log2_n2) < ks.n2) ++log2_n2;
+  ssfm::RowArgs ra{};
+  ra.field = field;
+  ra.tw = p->tw2;
+  ra.twA = p->twA;
+  ra.twB = p->twB;
+  ra.n1 = ks.n1;
+  ra.log2_n2 = log2_n2;
   ssfm::ColArgs a{};
   a.field = field;
   a.tw1 = p->tw1;
-  a.twA = p->twA;
-  a.twB = p->twB;
   a.n2 = ks.n2;
-  a.log2_n2 = 0;
-  while ((1 << a.log2_n2) < ks.n2) ++a.log2_n2;
   a.n = p->n;
   a.gspan = p->gspan;
   a.sigma_h = p->sigma_h;
@@ -288,9 +324,9 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
   for (int s = s0; s < s1; ++s) {
     a.span = s;
     for (int i = 0; i <= p->steps; ++i) {
-      const cd* H = (i == 0 || i == p->steps) ? p->h_half : p->h_full;
+      ra.H = (i == 0 || i == p->steps) ? p->h_half : p->h_full;
       if ((e = launch(p, KIND_ROW, field_bytes, st,
-                      [&] { return row(field, H, p->tw2, ks.n1, rows, st); })) != hipSuccess)
+                      [&] { return row(ra, rows, st); })) != hipSuccess)
         return fail_hip(e, "k2 launch");
       int mode;
       if (i < p->steps) {

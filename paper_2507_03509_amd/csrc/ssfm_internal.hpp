@@ -14,13 +14,20 @@ enum { MODE_FIRST = 0,   // time -> mixed domain (start of the link)
        MODE_EDFA = 2,    // mixed -> time, amplifier + ASE, time -> mixed
        MODE_LAST = 3 };  // mixed -> time, amplifier + ASE (end of the link)
 
+struct RowArgs {
+  float2* field;
+  const cd* H;       // dispersion operator in [k1][k2] order
+  const cd* tw;      // W_N2^m, m < N2
+  const cd* twA;     // W_N^{a N2}, a < N1
+  const cd* twB;     // W_N^{b}, b < N2
+  int n1;
+  int log2_n2;
+};
+
 struct ColArgs {
   float2* field;
   const cd* tw1;     // W_N1^m, m < N1
-  const cd* twA;     // W_N^{a N2}, a < N1
-  const cd* twB;     // W_N^{b}, b < N2
   int n2;
-  int log2_n2;
   int64_t n;         // N = N1 * N2 samples per polarisation
   double kappa;      // nonlinear coefficient of this step (MODE_NL)
   double gspan;      // field factor at the span end (MODE_EDFA, MODE_LAST)
@@ -44,7 +51,7 @@ struct LdsArgs {
   uint64_t realization0;
 };
 
-using RowLaunch = hipError_t (*)(float2*, const cd*, const cd*, int, int64_t, hipStream_t);
+using RowLaunch = hipError_t (*)(const RowArgs&, int64_t, hipStream_t);
 using ColLaunch = hipError_t (*)(const ColArgs&, int64_t, hipStream_t);
 using LdsLaunch = hipError_t (*)(const LdsArgs&, int64_t, hipStream_t);
 
@@ -60,7 +67,8 @@ struct KernelSet {
   LdsLaunch lds = nullptr;
   RowLaunch row_wide = nullptr, row_narrow = nullptr;
   int rows_wide = 0, rows_narrow = 0;  // rows per workgroup
-  FourStepKernels wide, narrow;
+  // column tiles: narrow (2 columns), mid, wide
+  FourStepKernels narrow, mid, wide;
   hipError_t prepare = hipSuccess;
 };
 

@@ -43,10 +43,26 @@ __device__ __forceinline__ cd round_c64(cd v) {
   return {(double)(float)v.re, (double)(float)v.im};
 }
 
-// exp(i phi) with phi given in FP64: FP32 sine/cosine, then one Newton step
-// on the modulus in FP64 so the rotation is unit-modulus to ~1e-15 (a rotation
-// whose modulus is off by an FP32 rounding would bias the power every step).
+// exp(i phi) in FP64.  For |phi| <= 1/4 (the nonlinear phase of one split
+// step is ~1e-2 rad on the workloads here) the Taylor series of sin to phi^11
+// and cos to phi^10, truncation below 1e-15 relative, so the rotation is
+// unit-modulus to FP64 rounding.  Larger angles: single-precision sine and
+// cosine, then one Newton step on the modulus in FP64 (a rotation whose
+// modulus carries a single-precision rounding would bias the power at every
+// step).
 __device__ __forceinline__ cd unit_phasor(double phi) {
+  if (fabs(phi) <= 0.25) {
+    const double x2 = phi * phi;
+    double ps = fma(x2, -1.0 / 39916800.0, 1.0 / 362880.0);
+    ps = fma(ps, x2, -1.0 / 5040.0);
+    ps = fma(ps, x2, 1.0 / 120.0);
+    ps = fma(ps, x2, -1.0 / 6.0);
+    double pc = fma(x2, -1.0 / 3628800.0, 1.0 / 40320.0);
+    pc = fma(pc, x2, -1.0 / 720.0);
+    pc = fma(pc, x2, 1.0 / 24.0);
+    pc = fma(pc, x2, -0.5);
+    return {fma(pc, x2, 1.0), fma(ps * x2, phi, phi)};
+  }
   float s, c;
   sincosf((float)phi, &s, &c);
   const double cr = c, sr = s;
@@ -55,30 +71,59 @@ __device__ __forceinline__ cd unit_phasor(double phi) {
   return {cr * f, sr * f};
 }
 
+// twiddle W_N^m from the two-level table (m < N): twA[a] = W_N^{a N2},
+// twB[b] = W_N^b
+__device__ __forceinline__ cd four_step_twiddle(const cd* __restrict__ twA,
+                                                const cd* __restrict__ twB, int m, int log2_n2,
+                                                int n2) {
+  return cmul(twA[m >> log2_n2], twB[m & (n2 - 1)]);
+}
+
 // ---------------------------------------------------------------------------
 // K2: rows of length N2 (contiguous), WG lanes, FP32 LDS exchange.
 // ---------------------------------------------------------------------------
-template <int N2, int WG>
-__global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field,
-                                              const cd* __restrict__ H, const cd* __restrict__ tw,
-                                              int n1) {
+template <int N2, int WG, typename L>
+__global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field, const cd* __restrict__ H,
+                                              const cd* __restrict__ tw,
+                                              const cd* __restrict__ twA,
+                                              const cd* __restrict__ twB, int n1, int log2_n2) {
   constexpr int T = N2 / 16;
   constexpr int RPW = WG / T;
-  extern __shared__ float2 lds2[];
+  extern __shared__ __align__(16) unsigned char lds2_raw[];
+  L* lds2 = reinterpret_cast<L*>(lds2_raw);
   const int lr = threadIdx.x / T;
   const int j = threadIdx.x % T;
   const int64_t row = (int64_t)blockIdx.x * RPW + lr;
   const int k1 = (int)(row % n1);
   float2* rp = field + row * N2;
-  float2* mylds = lds2 + lr * N2;
+  L* mylds = lds2 + lr * (N2 + N2 / 16);  // padded row: stride = 16 mod 32 slots
   cd reg[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) reg[r] = load_c64(rp + j + T * r);
-  fft<N2, false>(reg, mylds, 1, j, tw);
+  // four-step twiddle W_N^{n2 k1} on n2 = j + T r: W_N^{k1 j} (W_N^{k1 T})^r
+  const cd w0 = four_step_twiddle(twA, twB, k1 * j, log2_n2, N2);
+  const cd wstep = four_step_twiddle(twA, twB, k1 * T, log2_n2, N2);
+  {
+    cd w = w0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      reg[r] = cmul(reg[r], w);
+      if (r < 15) w = cmul(w, wstep);
+    }
+  }
+  fft<N2, false, true>(reg, mylds, 1, j, tw);
   const cd* hp = H + (int64_t)k1 * N2;
 #pragma unroll
   for (int r = 0; r < 16; ++r) reg[r] = cmul(reg[r], hp[j + T * r]);
-  fft<N2, true>(reg, mylds, 1, j, tw);
+  fft<N2, true, true>(reg, mylds, 1, j, tw);
+  {
+    cd w = w0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      reg[r] = cmulc(reg[r], w);
+      if (r < 15) w = cmul(w, wstep);
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) store_c64(rp + j + T * r, reg[r]);
 }
@@ -88,16 +133,11 @@ __global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field,
 // ---------------------------------------------------------------------------
 
 
-// twiddle W_N^{n2 k1} from the two-level table (n2 k1 < N, no reduction)
-__device__ __forceinline__ cd four_step_twiddle(const ColArgs& a, int n2, int k1) {
-  const int m = n2 * k1;
-  return cmul(a.twA[m >> a.log2_n2], a.twB[m & (a.n2 - 1)]);
-}
-
-template <int N1, int C, int P, int MODE>
+template <int N1, int C, int P, int MODE, typename L>
 __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
   constexpr int T = N1 / 16;
-  extern __shared__ float2 lds3[];
+  extern __shared__ __align__(16) unsigned char lds3_raw[];
+  L* lds3 = reinterpret_cast<L*>(lds3_raw);
   const int tid = threadIdx.x;
   const int p = tid / (C * T);
   const int rem = tid % (C * T);
@@ -107,55 +147,58 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
   const int64_t b = blockIdx.x / tiles;
   const int n2 = (int)(blockIdx.x % tiles) * C + c;
   float2* fp = a.field + (b * P + p) * a.n + n2;
-  float2* mylds = lds3 + p * (N1 * C) + c;
+  L* mylds = lds3 + p * (N1 * C) + c;
   cd reg[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) reg[r] = load_c64(fp + (int64_t)(j + T * r) * a.n2);
 
   if constexpr (MODE != MODE_FIRST) {
-    // mixed (k1, n2) domain -> time: conjugate twiddle, inverse column FFT
-#pragma unroll
-    for (int r = 0; r < 16; ++r) reg[r] = cmulc(reg[r], four_step_twiddle(a, n2, j + T * r));
-    fft<N1, true>(reg, mylds, C, j, a.tw1);
+    // mixed (k1, n2) domain -> time: inverse column FFT
+    fft<N1, true, false>(reg, mylds, C, j, a.tw1);
     if constexpr (MODE == MODE_NL) {
-      double pw[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) pw[r] = fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im);
       if constexpr (P == 2) {
-        // exchange |a_p|^2 with the lane of the other polarisation
-        double* pbuf = reinterpret_cast<double*>(lds3);
+        // exchange |a_p|^2 with the lane of the other polarisation (the sum
+        // is formed x + y on both lanes, so both rotate by the same phase)
+        double* pbuf = reinterpret_cast<double*>(lds3_raw);
         __syncthreads();  // the inverse FFT's LDS reads are done
 #pragma unroll
-        for (int r = 0; r < 16; ++r) pbuf[p * (N1 * C) + (j + T * r) * C + c] = pw[r];
+        for (int r = 0; r < 16; ++r)
+          pbuf[p * (N1 * C) + (j + T * r) * C + c] = fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im);
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const double other = pbuf[(1 - p) * (N1 * C) + (j + T * r) * C + c];
-          pw[r] = p == 0 ? pw[r] + other : other + pw[r];
+          const int i = (j + T * r) * C + c;
+          const double pw = pbuf[i] + pbuf[N1 * C + i];
+          reg[r] = cmul(reg[r], unit_phasor(a.kappa * pw));
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const double pw = fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im);
+          reg[r] = cmul(reg[r], unit_phasor(a.kappa * pw));
         }
       }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) reg[r] = cmul(reg[r], unit_phasor(a.kappa * pw[r]));
     } else {
       // amplifier: a <- gspan a + ASE(t), t = n1 N2 + n2.  The noise is drawn
       // in a rolled loop into this lane's own LDS slots and added back in an
       // unrolled one, so the field registers are never indexed at run time.
       const uint64_t key1 = (a.realization0 + (uint64_t)b) * 65536ull + (uint64_t)a.span;
       const bool noisy = a.sigma_h != 0.0;
+      float2* nbuf = reinterpret_cast<float2*>(lds3_raw) + p * (N1 * C) + c;
       if (noisy) {
         __syncthreads();  // the inverse FFT's LDS reads are done
 #pragma unroll 1
         for (int r = 0; r < 16; ++r) {
           const uint64_t t = (uint64_t)(j + T * r) * (uint64_t)a.n2 + (uint64_t)n2;
           const u64x4 w = philox4x64_10(t, 0, 0, 0, a.seed, key1);
-          mylds[(j + T * r) * C] = p == 0 ? box_muller(w.w[0], w.w[1]) : box_muller(w.w[2], w.w[3]);
+          nbuf[(j + T * r) * C] = p == 0 ? box_muller(w.w[0], w.w[1]) : box_muller(w.w[2], w.w[3]);
         }
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         cd v = cscale(reg[r], a.gspan);
         if (noisy) {
-          const float2 g = mylds[(j + T * r) * C];
+          const float2 g = nbuf[(j + T * r) * C];
           v.re = fma(a.sigma_h, (double)g.x, v.re);
           v.im = fma(a.sigma_h, (double)g.y, v.im);
         }
@@ -164,10 +207,8 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
     }
   }
   if constexpr (MODE != MODE_LAST) {
-    // time -> mixed domain: column FFT, twiddle
-    fft<N1, false>(reg, mylds, C, j, a.tw1);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) reg[r] = cmul(reg[r], four_step_twiddle(a, n2, j + T * r));
+    // time -> mixed domain: column FFT
+    fft<N1, false, false>(reg, mylds, C, j, a.tw1);
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
@@ -179,10 +220,12 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
 // ---------------------------------------------------------------------------
 
 
-template <int N, int P>
+template <int N, int P, typename L>
 __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
   constexpr int T = N / 16;
-  extern __shared__ float2 lds1[];
+  extern __shared__ __align__(16) unsigned char lds1_raw[];
+  L* lds1 = reinterpret_cast<L*>(lds1_raw);
+  float2* nbuf = reinterpret_cast<float2*>(lds1_raw);
   const int jj = threadIdx.x;  // the block is exactly T lanes
   const int64_t b = blockIdx.x;
   float2* fp = a.field + b * P * N;
@@ -209,14 +252,14 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
         }
       }
       const cd* h = (i == 0 || i == a.steps) ? a.h_half : a.h_full;
-      fft_multi<N, false, P>(reg, lds1, N, 1, jj, a.tw);
+      fft_multi<N, false, P, true>(reg, lds1, N + N / 16, 1, jj, a.tw);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const cd hv = h[jj + T * r];
 #pragma unroll
         for (int q = 0; q < P; ++q) reg[q][r] = cmul(reg[q][r], hv);
       }
-      fft_multi<N, true, P>(reg, lds1, N, 1, jj, a.tw);
+      fft_multi<N, true, P, true>(reg, lds1, N + N / 16, 1, jj, a.tw);
     }
     // span end: loss factor, amplifier gain, ASE (drawn into this lane's own
     // LDS slots in a rolled loop, then added in an unrolled one)
@@ -226,8 +269,8 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
 #pragma unroll 1
       for (int r = 0; r < 16; ++r) {
         const u64x4 w = philox4x64_10((uint64_t)(jj + T * r), 0, 0, 0, a.seed, rkey + (uint64_t)s);
-        lds1[jj + T * r] = box_muller(w.w[0], w.w[1]);
-        if (P == 2) lds1[N + jj + T * r] = box_muller(w.w[2], w.w[3]);
+        nbuf[jj + T * r] = box_muller(w.w[0], w.w[1]);
+        if (P == 2) nbuf[N + jj + T * r] = box_muller(w.w[2], w.w[3]);
       }
     }
 #pragma unroll
@@ -236,7 +279,7 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
       for (int q = 0; q < P; ++q) {
         reg[q][r] = cscale(reg[q][r], a.gspan);
         if (noisy) {
-          const float2 g = lds1[q * N + jj + T * r];
+          const float2 g = nbuf[q * N + jj + T * r];
           reg[q][r].re = fma(a.sigma_h, (double)g.x, reg[q][r].re);
           reg[q][r].im = fma(a.sigma_h, (double)g.y, reg[q][r].im);
         }
@@ -253,48 +296,69 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
 // ---------------------------------------------------------------------------
 // Launchers (host side): one function per instantiation, selected at plan time.
 // ---------------------------------------------------------------------------
-template <int N2, int WG>
-static hipError_t launch_k2(float2* field, const cd* H, const cd* tw, int n1, int64_t rows,
-                            hipStream_t st) {
+template <int N2, int WG, typename L>
+static hipError_t launch_k2(const RowArgs& a, int64_t rows, hipStream_t st) {
   constexpr int T = N2 / 16;
   constexpr int RPW = WG / T;
-  const size_t lds = (size_t)RPW * N2 * sizeof(float2);
-  hipLaunchKernelGGL((k2_rows<N2, WG>), dim3((unsigned)(rows / RPW)), dim3(WG), lds, st, field,
-                     H, tw, n1);
+  const size_t lds = (size_t)RPW * (N2 + N2 / 16) * sizeof(L);
+  hipLaunchKernelGGL((k2_rows<N2, WG, L>), dim3((unsigned)(rows / RPW)), dim3(WG), lds, st,
+                     a.field, a.H, a.tw, a.twA, a.twB, a.n1, a.log2_n2);
   return hipGetLastError();
 }
 
-template <int N1, int C, int P, int MODE>
-static hipError_t launch_k3(const ColArgs& a, int64_t batch, hipStream_t st) {
-  constexpr int T = N1 / 16;
-  const size_t lds = (size_t)P * C * N1 * sizeof(double);  // power exchange needs 8 B/elem
-  const unsigned blocks = (unsigned)(batch * (a.n2 / C));
-  hipLaunchKernelGGL((k3_cols<N1, C, P, MODE>), dim3(blocks), dim3(P * C * T), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int N, int P>
-static hipError_t launch_k1(const LdsArgs& a, int64_t batch, hipStream_t st) {
-  constexpr int T = N / 16;
-  const size_t lds = (size_t)P * N * sizeof(float2);
-  hipLaunchKernelGGL((k1_lds<N, P>), dim3((unsigned)batch), dim3(T), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int N, int P>
-static hipError_t prepare_k1() {
-  const size_t lds = (size_t)P * N * sizeof(float2);
+template <int N2, int WG, typename L>
+static hipError_t prepare_k2() {
+  constexpr int T = N2 / 16;
+  const size_t lds = (size_t)(WG / T) * (N2 + N2 / 16) * sizeof(L);
   if (lds > 65536)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k1_lds<N, P>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_rows<N2, WG, L>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   return hipSuccess;
 }
 
-template <int N1, int C, int P, int MODE>
-static hipError_t prepare_k3_one() {
-  const size_t lds = (size_t)P * C * N1 * sizeof(double);
+template <int N1, int C, int P, int MODE, typename L>
+constexpr size_t k3_lds_bytes() {
+  // FFT exchange: P*C*N1 elements of L; nonlinear step: P*C*N1 doubles;
+  // noise staging: P*C*N1 float2
+  return (size_t)P * C * N1 * (sizeof(L) > 8 ? sizeof(L) : 8);
+}
+
+template <int N1, int C, int P, int MODE, typename L>
+static hipError_t launch_k3(const ColArgs& a, int64_t batch, hipStream_t st) {
+  constexpr int T = N1 / 16;
+  const unsigned blocks = (unsigned)(batch * (a.n2 / C));
+  const size_t lds = k3_lds_bytes<N1, C, P, MODE, L>();
+  hipLaunchKernelGGL((k3_cols<N1, C, P, MODE, L>), dim3(blocks), dim3(P * C * T), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int N, int P, typename L>
+constexpr size_t k1_lds_bytes() {
+  return (size_t)P * (N + N / 16) * sizeof(L);
+}
+
+template <int N, int P, typename L>
+static hipError_t launch_k1(const LdsArgs& a, int64_t batch, hipStream_t st) {
+  constexpr int T = N / 16;
+  const size_t lds = k1_lds_bytes<N, P, L>();
+  hipLaunchKernelGGL((k1_lds<N, P, L>), dim3((unsigned)batch), dim3(T), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int N, int P, typename L>
+static hipError_t prepare_k1() {
+  const size_t lds = k1_lds_bytes<N, P, L>();
   if (lds > 65536)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_cols<N1, C, P, MODE>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k1_lds<N, P, L>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
+template <int N1, int C, int P, int MODE, typename L>
+static hipError_t prepare_k3_one() {
+  const size_t lds = k3_lds_bytes<N1, C, P, MODE, L>();
+  if (lds > 65536)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_cols<N1, C, P, MODE, L>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   return hipSuccess;
 }
@@ -307,26 +371,32 @@ static int log2i(int64_t v) {
   return l;
 }
 
-template <int N1, int C, int P>
+template <int N1, int C, int P, typename L>
 static void fill_k3(FourStepKernels& k) {
-  k.col[MODE_FIRST] = &launch_k3<N1, C, P, MODE_FIRST>;
-  k.col[MODE_NL] = &launch_k3<N1, C, P, MODE_NL>;
-  k.col[MODE_EDFA] = &launch_k3<N1, C, P, MODE_EDFA>;
-  k.col[MODE_LAST] = &launch_k3<N1, C, P, MODE_LAST>;
+  k.col[MODE_FIRST] = &launch_k3<N1, C, P, MODE_FIRST, L>;
+  k.col[MODE_NL] = &launch_k3<N1, C, P, MODE_NL, L>;
+  k.col[MODE_EDFA] = &launch_k3<N1, C, P, MODE_EDFA, L>;
+  k.col[MODE_LAST] = &launch_k3<N1, C, P, MODE_LAST, L>;
   k.columns = C;
-  k.prepare_status = prepare_k3_one<N1, C, P, MODE_FIRST>();
-  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_NL>();
-  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_EDFA>();
-  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_LAST>();
+  k.prepare_status = prepare_k3_one<N1, C, P, MODE_FIRST, L>();
+  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_NL, L>();
+  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_EDFA, L>();
+  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_LAST, L>();
 }
 
 template <int N1, int P>
-static void fill_cols(FourStepKernels& wide, FourStepKernels& narrow) {
-  // wide tiles: 16 (8 at N1 = 512) adjacent columns, 128/64-byte row segments;
-  // narrow tiles: 2 columns, for batches too small to fill the chip
-  if constexpr (N1 == 512) fill_k3<N1, 8, P>(wide);
-  else fill_k3<N1, 16, P>(wide);
-  fill_k3<N1, 2, P>(narrow);
+static void fill_cols(KernelSet& ks) {
+  // FFT exchanges in FP64 LDS, 64 KB per workgroup for the wide tiles: 8 (4 at
+  // N1 = 512) adjacent columns, 64/32-byte row segments; mid tiles: half of
+  // that; narrow tiles: 2 columns, for batches too small to fill the chip
+  if constexpr (N1 == 512) {
+    fill_k3<N1, 4, P, cd>(ks.wide);
+    fill_k3<N1, 8, P, float2>(ks.mid);
+  } else {
+    fill_k3<N1, 8, P, cd>(ks.wide);
+    fill_k3<N1, 16, P, float2>(ks.mid);
+  }
+  fill_k3<N1, 2, P, cd>(ks.narrow);
 }
 
 bool select_kernels(int64_t n, int n_pol, KernelSet& ks) {
@@ -334,13 +404,15 @@ bool select_kernels(int64_t n, int n_pol, KernelSet& ks) {
   ks = KernelSet{};
   if (l <= 13) {
     ks.path = 1;
-#define K1CASE(LN)                                                           \
-  case LN:                                                                   \
-    if (n_pol == 1) { ks.lds = &launch_k1<(1 << LN), 1>; ks.prepare = prepare_k1<(1 << LN), 1>(); } \
-    else { ks.lds = &launch_k1<(1 << LN), 2>; ks.prepare = prepare_k1<(1 << LN), 2>(); } \
+// FP64 LDS exchange where the padded field fits in 160 KB, else FP32
+#define K1CASE(LN, L2)                                                                          \
+  case LN:                                                                                      \
+    if (n_pol == 1) { ks.lds = &launch_k1<(1 << LN), 1, cd>; ks.prepare = prepare_k1<(1 << LN), 1, cd>(); } \
+    else { ks.lds = &launch_k1<(1 << LN), 2, L2>; ks.prepare = prepare_k1<(1 << LN), 2, L2>(); } \
     return true;
     switch (l) {
-      K1CASE(6) K1CASE(7) K1CASE(8) K1CASE(9) K1CASE(10) K1CASE(11) K1CASE(12) K1CASE(13)
+      K1CASE(6, cd) K1CASE(7, cd) K1CASE(8, cd) K1CASE(9, cd) K1CASE(10, cd) K1CASE(11, cd)
+      K1CASE(12, cd) K1CASE(13, float2)
       default: return false;
     }
 #undef K1CASE
@@ -349,19 +421,22 @@ bool select_kernels(int64_t n, int n_pol, KernelSet& ks) {
   const int l1 = l / 2;
   ks.n1 = 1 << l1;
   ks.n2 = (int)(n >> l1);
+  hipError_t pr = hipSuccess;
   switch (ks.n2) {
-    case 128: ks.row_wide = &launch_k2<128, 256>; ks.row_narrow = &launch_k2<128, 64>; ks.rows_narrow = 64 / 8; ks.rows_wide = 256 / 8; break;
-    case 256: ks.row_wide = &launch_k2<256, 256>; ks.row_narrow = &launch_k2<256, 64>; ks.rows_narrow = 64 / 16; ks.rows_wide = 256 / 16; break;
-    case 512: ks.row_wide = &launch_k2<512, 256>; ks.row_narrow = &launch_k2<512, 64>; ks.rows_narrow = 64 / 32; ks.rows_wide = 256 / 32; break;
+    case 128: ks.row_wide = &launch_k2<128, 256, cd>; ks.row_narrow = &launch_k2<128, 64, cd>; ks.rows_narrow = 64 / 8; ks.rows_wide = 256 / 8; pr = prepare_k2<128, 256, cd>(); break;
+    case 256: ks.row_wide = &launch_k2<256, 256, cd>; ks.row_narrow = &launch_k2<256, 64, cd>; ks.rows_narrow = 64 / 16; ks.rows_wide = 256 / 16; pr = prepare_k2<256, 256, cd>(); break;
+    case 512: ks.row_wide = &launch_k2<512, 256, cd>; ks.row_narrow = &launch_k2<512, 64, cd>; ks.rows_narrow = 64 / 32; ks.rows_wide = 256 / 32; pr = prepare_k2<512, 256, cd>(); break;
     default: return false;
   }
+  if (pr != hipSuccess) ks.prepare = pr;
   switch (ks.n1) {
-    case 128: if (n_pol == 1) fill_cols<128, 1>(ks.wide, ks.narrow); else fill_cols<128, 2>(ks.wide, ks.narrow); break;
-    case 256: if (n_pol == 1) fill_cols<256, 1>(ks.wide, ks.narrow); else fill_cols<256, 2>(ks.wide, ks.narrow); break;
-    case 512: if (n_pol == 1) fill_cols<512, 1>(ks.wide, ks.narrow); else fill_cols<512, 2>(ks.wide, ks.narrow); break;
+    case 128: if (n_pol == 1) fill_cols<128, 1>(ks); else fill_cols<128, 2>(ks); break;
+    case 256: if (n_pol == 1) fill_cols<256, 1>(ks); else fill_cols<256, 2>(ks); break;
+    case 512: if (n_pol == 1) fill_cols<512, 1>(ks); else fill_cols<512, 2>(ks); break;
     default: return false;
   }
-  ks.prepare = ks.wide.prepare_status != hipSuccess ? ks.wide.prepare_status : ks.narrow.prepare_status;
+  for (const FourStepKernels* k : {&ks.wide, &ks.mid, &ks.narrow})
+    if (k->prepare_status != hipSuccess) ks.prepare = k->prepare_status;
   return true;
 }
 
