@@ -187,6 +187,23 @@ struct fft_shape {
   static constexpr int tw_offset(int p) { return fft_tw_offset(log2m, p); }
 };
 
+// Synchronisation of the LDS exchanges.  A transform carried by one wave
+// only needs its own LDS accesses kept in program order (the LDS executes a
+// wave's instructions in order), so a wavefront-scope fence pair suffices and
+// no block barrier -- which would also wait for every outstanding global->LDS
+// copy of the block -- is needed.  Transforms spanning several waves use a
+// block barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <bool WAVE>
+__device__ __forceinline__ void xsync() {
+  if constexpr (WAVE) wave_sync();
+  else __syncthreads();
+}
+
 // LDS element conversions: FP64 values are held as cd or rounded to float2.
 __device__ __forceinline__ void lds_put(cd* p, cd v) { *p = v; }
 __device__ __forceinline__ void lds_put(float2* p, cd v) {
@@ -263,20 +280,20 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
   }
 }
 
-template <int M, bool INV, int P, int NT, bool PAD, typename L>
+template <int M, bool INV, int P, int NT, bool PAD, bool WAVE, typename L>
 __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride, int ls,
                                          int j, const cd* __restrict__ tw) {
   using S = fft_shape<M>;
   if constexpr (P < S::passes) {
     constexpr bool last = P == S::passes - 1;
-    __syncthreads();  // writes of the previous pass are visible
+    xsync<WAVE>();  // writes of the previous pass are visible
 #pragma unroll
     for (int t = 0; t < NT; ++t) pass_load<M, P, PAD>(reg[t], lds + t * tstride, ls, j);
-    if constexpr (!last) __syncthreads();  // all reads done before overwriting
+    if constexpr (!last) xsync<WAVE>();  // all reads done before overwriting
 #pragma unroll
     for (int t = 0; t < NT; ++t)
       pass_compute<M, P, INV, last, PAD>(reg[t], lds + t * tstride, ls, j, tw);
-    fft_rest<M, INV, P + 1, NT, PAD>(reg, lds, tstride, ls, j, tw);
+    fft_rest<M, INV, P + 1, NT, PAD, WAVE>(reg, lds, tstride, ls, j, tw);
   }
 }
 
@@ -284,10 +301,12 @@ __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride,
 // barriers); transform t uses the LDS region starting at lds + t * tstride.
 // Lane j holds elements j + (M/16) r of each transform on entry and on exit.
 // Forward uses exp(-2 pi i nk/M), inverse exp(+2 pi i nk/M).
-// Contains block-wide barriers: every lane of the block must call it.
+// Contains barriers (see fft_multi).
 // PAD selects the padded slot map for contiguous transforms (ls = 1); a
-// padded transform occupies M + M/16 slots.
-template <int M, bool INV, int NT, bool PAD, typename L>
+// padded transform occupies M + M/16 slots.  WAVE: every lane sharing the LDS
+// regions is in the calling wave (see xsync); otherwise the whole block must
+// call.
+template <int M, bool INV, int NT, bool PAD, bool WAVE, typename L>
 __device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride, int ls,
                                           int j, const cd* __restrict__ tw) {
   using S = fft_shape<M>;
@@ -295,18 +314,18 @@ __device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride
 #pragma unroll
     for (int t = 0; t < NT; ++t) pass_compute<M, 0, INV, true, PAD>(reg[t], lds, ls, j, tw);
   } else {
-    __syncthreads();  // earlier readers of the LDS regions are done
+    xsync<WAVE>();  // earlier readers of the LDS regions are done
 #pragma unroll
     for (int t = 0; t < NT; ++t)
       pass_compute<M, 0, INV, false, PAD>(reg[t], lds + t * tstride, ls, j, tw);
-    fft_rest<M, INV, 1, NT, PAD>(reg, lds, tstride, ls, j, tw);
+    fft_rest<M, INV, 1, NT, PAD, WAVE>(reg, lds, tstride, ls, j, tw);
   }
 }
 
-template <int M, bool INV, bool PAD, typename L>
+template <int M, bool INV, bool PAD, bool WAVE, typename L>
 __device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
                                     const cd* __restrict__ tw) {
-  fft_multi<M, INV, 1, PAD>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);
+  fft_multi<M, INV, 1, PAD, WAVE>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);
 }
 
 }  // namespace ssfm

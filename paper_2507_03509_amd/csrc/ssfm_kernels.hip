@@ -111,11 +111,11 @@ __global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field, const 
       if (r < 15) w = cmul(w, wstep);
     }
   }
-  fft<N2, false, true>(reg, mylds, 1, j, tw);
+  fft<N2, false, true, true>(reg, mylds, 1, j, tw);  // one wave per row
   const cd* hp = H + (int64_t)k1 * N2;
 #pragma unroll
   for (int r = 0; r < 16; ++r) reg[r] = cmul(reg[r], hp[j + T * r]);
-  fft<N2, true, true>(reg, mylds, 1, j, tw);
+  fft<N2, true, true, true>(reg, mylds, 1, j, tw);
   {
     cd w = w0;
 #pragma unroll
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
 
   if constexpr (MODE != MODE_FIRST) {
     // mixed (k1, n2) domain -> time: inverse column FFT
-    fft<N1, true, false>(reg, mylds, C, j, a.tw1);
+    fft<N1, true, false, false>(reg, mylds, C, j, a.tw1);
     if constexpr (MODE == MODE_NL) {
       if constexpr (P == 2) {
         // exchange |a_p|^2 with the lane of the other polarisation (the sum
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
   }
   if constexpr (MODE != MODE_LAST) {
     // time -> mixed domain: column FFT
-    fft<N1, false, false>(reg, mylds, C, j, a.tw1);
+    fft<N1, false, false, false>(reg, mylds, C, j, a.tw1);
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
@@ -252,14 +252,14 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
         }
       }
       const cd* h = (i == 0 || i == a.steps) ? a.h_half : a.h_full;
-      fft_multi<N, false, P, true>(reg, lds1, N + N / 16, 1, jj, a.tw);
+      fft_multi<N, false, P, true, false>(reg, lds1, N + N / 16, 1, jj, a.tw);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const cd hv = h[jj + T * r];
 #pragma unroll
         for (int q = 0; q < P; ++q) reg[q][r] = cmul(reg[q][r], hv);
       }
-      fft_multi<N, true, P, true>(reg, lds1, N + N / 16, 1, jj, a.tw);
+      fft_multi<N, true, P, true, false>(reg, lds1, N + N / 16, 1, jj, a.tw);
     }
     // span end: loss factor, amplifier gain, ASE (drawn into this lane's own
     // LDS slots in a rolled loop, then added in an unrolled one)
