@@ -144,8 +144,14 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
   const int c = rem % C;
   const int j = rem / C;
   const int tiles = a.n2 / C;
-  const int64_t b = blockIdx.x / tiles;
-  const int n2 = (int)(blockIdx.x % tiles) * C + c;
+  // Adjacent column tiles share 128-byte lines.  Workgroups are dispatched
+  // round-robin over the 8 XCDs (each with its own L2), so XCD x runs blocks
+  // x, x + 8, ...: give it the contiguous tile range [x G/8, (x + 1) G/8) so a
+  // line is fetched into one L2 only.
+  const unsigned G = gridDim.x;
+  const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int64_t b = id / tiles;
+  const int n2 = (int)(id % tiles) * C + c;
   float2* fp = a.field + (b * P + p) * a.n + n2;
   L* mylds = lds3 + p * (N1 * C) + c;
   cd reg[16];
