@@ -9,9 +9,9 @@ shares no code, tables or constants with the GPU path.
 from .ssfm_ref import (si_params, angular_frequency, linear_factor,
                        nl_step_length, linear_step, nl_step, ase_words,
                        uniform_from_words, ase_noise, edfa, propagate,
-                       propagate_batch)
+                       propagate_batch, nl_pullback, adjoint)
 
 __all__ = ["si_params", "angular_frequency", "linear_factor",
            "nl_step_length", "linear_step", "nl_step", "ase_words",
            "uniform_from_words", "ase_noise", "edfa", "propagate",
-           "propagate_batch"]
+           "propagate_batch", "nl_pullback", "adjoint"]

@@ -49,7 +49,7 @@ import numpy as np
 __all__ = ["si_params", "angular_frequency", "linear_factor",
            "nl_step_length", "linear_step", "nl_step", "ase_words",
            "uniform_from_words", "ase_noise", "edfa", "propagate",
-           "propagate_batch"]
+           "propagate_batch", "nl_pullback", "adjoint"]
 
 PLANCK = 6.62607015e-34          # J s (SI exact)
 DEFAULT_CARRIER_HZ = 193.4145e12  # 1550 nm
@@ -200,3 +200,64 @@ def propagate_batch(fields, link, seed: int = 0, realization0: int = 0,
     return np.stack([propagate(fields[b], link, seed, realization0 + b,
                                span_begin, span_end)
                      for b in range(fields.shape[0])])
+
+
+# ---------------------------------------------------------------------------
+# Adjoint (vector-Jacobian product) of the propagation, for gradients.
+#
+# For a real loss L and the conjugate Wirtinger derivatives g = dL/dA*, each
+# step of the scheme is pulled back exactly:
+#   linear step  y = ifft(H fft(x)):   g_x = ifft(conj(H) fft(g_y))
+#   nonlinear    y_p = x_p exp(i phi), phi = coef sum_q |x_q|^2:
+#                g_x_p = g_y_p exp(-i phi) + 2 s coef x_p,
+#                s = -Im(sum_q conj(g_y_q) y_q)
+#   amplifier    y = sqrt(G) x + noise:  g_x = sqrt(G) g_y
+# (chain rule on y(x, x*); the noise does not depend on the field).  The
+# forward states are stored, step by step, and the pullbacks applied in
+# reverse order.  The map from g_y to g_x is real-linear, so any constant
+# scaling of the incoming cotangent (e.g. PyTorch's factor 2) passes through.
+# ---------------------------------------------------------------------------
+
+def nl_pullback(x: np.ndarray, gy: np.ndarray, coef: float) -> np.ndarray:
+    power = np.sum(np.abs(x) ** 2, axis=0, keepdims=True)
+    rot = np.exp(1j * coef * power)
+    y = x * rot
+    s = -np.imag(np.sum(np.conj(gy) * y, axis=0, keepdims=True))
+    return gy * np.conj(rot) + 2.0 * s * coef * x
+
+
+def adjoint(field, grad_out, link, seed: int = 0, realization: int = 0) -> np.ndarray:
+    """dL/dA_in* given dL/dA_out* for propagate(field, link, seed, realization)."""
+    p = si_params(link)
+    a = np.array(field, dtype=np.complex128)
+    g = np.array(grad_out, dtype=np.complex128)
+    squeeze = a.ndim == 1
+    if squeeze:
+        a, g = a[None, :], g[None, :]
+    omega = angular_frequency(p["n"], p["fs"])
+    h = p["h"]
+    half = linear_factor(p["beta2"], p["alpha"], omega, h / 2.0)
+    full = linear_factor(p["beta2"], p["alpha"], omega, h)
+    coef = p["c_nl"] * p["gamma"] * nl_step_length(p["alpha"], h)
+    amplified = p["gain"] != 1.0 or p["ase"]
+    # forward, keeping the input of every nonlinear step
+    tape = []
+    for s in range(p["n_spans"]):
+        a = linear_step(a, half)
+        for j in range(p["steps"]):
+            tape.append(a)
+            a = nl_step(a, coef)
+            a = linear_step(a, full if j < p["steps"] - 1 else half)
+        if amplified:
+            a = edfa(a, p, seed, realization, s)
+    # reverse
+    k = len(tape)
+    for s in reversed(range(p["n_spans"])):
+        if amplified:
+            g = g * math.sqrt(p["gain"])
+        for j in reversed(range(p["steps"])):
+            g = linear_step(g, np.conj(full if j < p["steps"] - 1 else half))
+            k -= 1
+            g = nl_pullback(tape[k], g, coef)
+        g = linear_step(g, np.conj(half))
+    return g[0] if squeeze else g
