@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--single-steps", type=int, default=3,
                     help="timed calls of the batch-1 figure (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU time of the oracle baseline sample")
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="time one forward+adjoint call on the batch (0 to skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a "
                          "known-size reference for hardware traffic counters)")
@@ -171,6 +175,24 @@ def main() -> int:
                     for s in stats},
     }
 
+    # ---- forward + adjoint (one ssfm_adjoint call: forward with span
+    # checkpoints, then the reverse sweep) on the same batch -----------------
+    adj = None
+    if args.adjoint:
+        grad = field.clone()
+        plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)  # workspace + warm-up
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        ms_adj = a0.elapsed_time(a1)
+        adj = {"fwd_adjoint_ms": round(ms_adj, 3), "ratio_to_forward": round(ms_adj / ms_per_step, 3)}
+        log(f"forward+adjoint: {ms_adj:.3f} ms ({ms_adj / ms_per_step:.2f}x forward)")
+        del grad
+
     # ---- one field (batch 1): the latency-bound figure ----------------------
     single = None
     if args.single_steps > 0 and batch > 1:
@@ -194,18 +216,25 @@ def main() -> int:
     cpu = None
     rel_err = None
     if not args.no_cpu_baseline:
+        # realisation 0 doubles as the parity reference; further realisations
+        # (their own inputs and noise keys) until ~10 s of CPU work
         import oracle
         c0 = time.perf_counter()
         want = oracle.propagate(ref_in, link, seed=w.ase_seed, realization=0)
-        csec = time.perf_counter() - c0
+        done = 1
         rel_err = float(np.linalg.norm(gpu_out0 - want) / np.linalg.norm(want))
-        cpu = {"value": n * total_steps / csec, "unit": "sample-steps/s", "cores": 1,
+        while time.perf_counter() - c0 < args.cpu_seconds and done < min(distinct, 8):
+            oracle.propagate(host[done], link, seed=w.ase_seed, realization=done)
+            done += 1
+        csec = time.perf_counter() - c0
+        cpu = {"value": done * n * total_steps / csec, "unit": "sample-steps/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"1 realisation of the same link ({link.n_spans} spans x "
+               "sample": f"{done} realisation(s) of the same link ({link.n_spans} spans x "
                          f"{link.steps_per_span} steps, {n} samples x {p} pol), FP64 NumPy, "
                          f"{csec:.1f} s on {cpu_model()} ({os.cpu_count()} logical CPUs, "
                          "single-threaded FFT and elementwise ops)"}
-        log(f"oracle: {csec:.1f} s, rel err of GPU realisation 0 = {rel_err:.3e}")
+        log(f"oracle: {done} realisation(s) in {csec:.1f} s; rel err of GPU realisation 0 = "
+            f"{rel_err:.3e}")
 
     out = {
         "metric": METRIC, "value": value, "unit": "sample-steps/s", "n_gpus": 1,
@@ -218,7 +247,8 @@ def main() -> int:
                    "field_storage": "complex64", "linear_step_arithmetic": "f64",
                    "parallelism": "single-gpu"},
         "rel_err_vs_oracle": rel_err,
-        "fwd_adjoint_ms": None,
+        "fwd_adjoint_ms": adj["fwd_adjoint_ms"] if adj else None,
+        "fwd_adjoint_ratio": adj["ratio_to_forward"] if adj else None,
         "batch1": single,
         "roofline": roofline,
         "cpu_baseline": cpu,

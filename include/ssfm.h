@@ -126,9 +126,27 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
                        uint64_t seed, uint64_t realization0, int32_t span_begin,
                        int32_t span_end, void* stream);
 
-/* Adjoint (reverse-mode) propagation for gradients through the link.
- * Not implemented in this build: returns SSFM_EUNSUPPORTED after argument
- * validation. */
+/* Adjoint (reverse-mode) propagation: the vector-Jacobian product of
+ * ssfm_forward (seed, realisations 0..batch-1, all spans) at `field_in`.
+ *   field_in: device complex64 [batch][n_pol][n_samples], the forward input;
+ *             read only.
+ *   grad:     device complex64 of the same shape; on entry the cotangent
+ *             dL/dA_out* of a real loss L at the forward output, on exit
+ *             dL/dA_in* (any constant factor on the way in, such as the 2 of
+ *             PyTorch's complex gradients, carries through: the map is
+ *             real-linear in the cotangent).
+ * Method: a forward pass keeps the span-end states (span checkpoints); the
+ * reverse sweep then rebuilds each span's intermediate states from its
+ * checkpoint with the exact inverse steps (in the loss-free variable every
+ * linear and nonlinear step is unitary) while pulling the cotangent back
+ * through each step (linear: conj(H); nonlinear: g e^{-i phi} +
+ * 2 s coef x, s = -Im sum conj(g) y; amplifier: sqrt(G)).  Pullback formulas:
+ * chain rule in Wirtinger calculus for y = x exp(i coef sum|x|^2).
+ * Workspace: (n_spans + 2) * batch * n_pol * n_samples * 8 bytes, allocated
+ * on first use (and grown) and owned by the plan.  Asynchronous like
+ * ssfm_forward.  Errors: SSFM_EINVAL (NULL/misaligned pointers, batch < 1),
+ * SSFM_EUNSUPPORTED for n_samples < 2^14 (LDS-resident path), SSFM_ENOMEM,
+ * SSFM_EHIP. */
 int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
                  int64_t batch, uint64_t seed, void* stream);
 

@@ -22,7 +22,7 @@ __all__ = [
     "make_link", "ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info",
     "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch",
     "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
-    "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats",
+    "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats", "propagate",
     "SSFM_OK", "SSFM_EINVAL", "SSFM_ENOMEM", "SSFM_EHIP", "SSFM_EUNSUPPORTED",
 ]
 
@@ -260,9 +260,13 @@ def ssfm_forward_spans(plan: int, field, seed: int, realization0: int, span_begi
 
 
 def ssfm_adjoint(plan: int, field_in, grad, seed: int = 0, stream=None) -> None:
+    """grad (complex64 CUDA tensor shaped like field_in) holds dL/dA_out* on
+    entry and dL/dA_in* on exit; field_in is the forward input (read only)."""
     b, ptr = _field_args(field_in)
-    _, gptr = _field_args(grad)
-    _check(load_library().ssfm_adjoint(plan, ptr, gptr, b, int(seed),
+    bg, gptr = _field_args(grad)
+    if bg != b or tuple(grad.shape) != tuple(field_in.shape):
+        raise ValueError("grad must have the shape of field_in")
+    _check(load_library().ssfm_adjoint(plan, ptr, gptr, b, int(seed) & (2 ** 64 - 1),
                                        _stream_ptr(field_in, stream)), "ssfm_adjoint")
 
 
@@ -301,6 +305,12 @@ class Plan:
                            stream)
         return field
 
+    def adjoint(self, field_in, grad, seed: int = 0, stream=None):
+        """In-place on ``grad``: dL/dA_out* -> dL/dA_in* (see ssfm_adjoint)."""
+        _field_args(field_in, self.n_pol, self.n_samples)
+        ssfm_adjoint(self.handle, field_in, grad, seed, stream)
+        return grad
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             ssfm_plan_destroy(self.handle)
@@ -311,3 +321,43 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class Propagate(torch.autograd.Function):
+        """Differentiable propagation: forward by ssfm_forward, backward by
+        ssfm_adjoint (PyTorch's complex-gradient convention, 2 dL/dz*, is
+        carried through unchanged: the pullback is real-linear)."""
+
+        @staticmethod
+        def forward(ctx, field, plan, seed):
+            x = field.detach().contiguous()
+            out = x.clone()
+            plan.forward(out, seed=seed)
+            ctx.save_for_backward(x)
+            ctx.plan = plan
+            ctx.seed = seed
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (x,) = ctx.saved_tensors
+            g = grad_out.detach().to(torch.complex64).contiguous().clone()
+            ctx.plan.adjoint(x, g, seed=ctx.seed)
+            return g, None, None
+
+    return Propagate
+
+
+_Propagate = None
+
+
+def propagate(field, plan: "Plan", seed: int = 0):
+    """Autograd-aware propagation of a complex64 CUDA tensor through
+    ``plan``'s link (out of place)."""
+    global _Propagate
+    if _Propagate is None:
+        _Propagate = _autograd_function()
+    return _Propagate.apply(field, plan, seed)

@@ -80,10 +80,17 @@ struct ssfm_plan_s {
   size_t events_used = 0;
   std::vector<int> prof_kind;
   std::vector<double> prof_bytes;
+  // adjoint workspace (grown on demand): span checkpoints and the
+  // [state; cotangent] work buffer
+  float2* adj_ckpt = nullptr;
+  float2* adj_work = nullptr;
+  size_t adj_ckpt_bytes = 0, adj_work_bytes = 0;
 
   ~ssfm_plan_s() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     for (void* p : allocations) (void)hipFree(p);
+    if (adj_ckpt) (void)hipFree(adj_ckpt);
+    if (adj_work) (void)hipFree(adj_work);
   }
 };
 
@@ -218,8 +225,8 @@ int build_tables(ssfm_plan_s* p) {
   return SSFM_OK;
 }
 
-enum { KIND_LDS = 0, KIND_ROW = 1, KIND_COL = 2, KIND_COUNT = 3 };
-const char* const kKindName[KIND_COUNT] = {"k1_lds", "k2_rows", "k3_cols"};
+enum { KIND_LDS = 0, KIND_ROW = 1, KIND_COL = 2, KIND_ADJ = 3, KIND_COUNT = 4 };
+const char* const kKindName[KIND_COUNT] = {"k1_lds", "k2_rows", "k3_cols", "k3_adj"};
 
 hipError_t next_event(ssfm_plan_s* p, hipEvent_t* ev) {
   if (p->events_used == p->events.size()) {
@@ -272,7 +279,7 @@ const ssfm::FourStepKernels& pick_cols(const ssfm_plan_s* p, int64_t batch, bool
 }
 
 int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uint64_t real0,
-                int s0, int s1, hipStream_t st) {
+                int s0, int s1, hipStream_t st, float2* ckpt = nullptr) {
   const ssfm::KernelSet& ks = p->ks;
   hipError_t e;
   if (s0 == s1) return SSFM_OK;
@@ -309,6 +316,7 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
   ra.twB = p->twB;
   ra.n1 = ks.n1;
   ra.log2_n2 = log2_n2;
+  ra.conj_h = 0;
   ssfm::ColArgs a{};
   a.field = field;
   a.tw1 = p->tw1;
@@ -334,6 +342,7 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
         a.kappa = p->kappa[(size_t)i];
       } else {
         mode = s + 1 < s1 ? ssfm::MODE_EDFA : ssfm::MODE_LAST;
+        a.ckpt = ckpt ? ckpt + (size_t)s * batch * p->n_pol * p->n : nullptr;
       }
       if ((e = launch(p, KIND_COL, field_bytes, st,
                       [&] { return cols.col[mode](a, batch, st); })) != hipSuccess)
@@ -439,13 +448,97 @@ int ssfm_forward(ssfm_plan_t plan, void* field, int64_t batch, uint64_t seed, vo
 
 int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t batch,
                  uint64_t seed, void* stream) {
-  (void)seed;
-  (void)stream;
   g_last_error.clear();
   int rc = check_call(plan, field_in, batch);
   if (rc != SSFM_OK) return rc;
   if (!grad) return fail(SSFM_EINVAL, "grad is NULL");
-  return fail(SSFM_EUNSUPPORTED, "ssfm_adjoint is not implemented in this build");
+  if (((uintptr_t)grad & 7u) != 0) return fail(SSFM_EINVAL, "grad must be 8-byte aligned");
+  if (plan->ks.path != 2)
+    return fail(SSFM_EUNSUPPORTED, "ssfm_adjoint needs n_samples >= 2^14 (four-step path)");
+  DeviceGuard guard(plan->device);
+  if (guard.status != hipSuccess) return fail_hip(guard.status, "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const ssfm::KernelSet& ks = plan->ks;
+  const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
+  const size_t ckpt_bytes = (size_t)plan->spans * slice * sizeof(float2);
+  const size_t work_bytes = 2 * slice * sizeof(float2);
+  hipError_t e;
+  if (ckpt_bytes > plan->adj_ckpt_bytes || work_bytes > plan->adj_work_bytes) {
+    // grow the workspace (hipFree waits for work still using the old one)
+    if (plan->adj_ckpt) (void)hipFree(plan->adj_ckpt);
+    if (plan->adj_work) (void)hipFree(plan->adj_work);
+    plan->adj_ckpt = plan->adj_work = nullptr;
+    plan->adj_ckpt_bytes = plan->adj_work_bytes = 0;
+    if (hipMalloc(&plan->adj_ckpt, ckpt_bytes) != hipSuccess ||
+        hipMalloc(&plan->adj_work, work_bytes) != hipSuccess) {
+      if (plan->adj_ckpt) (void)hipFree(plan->adj_ckpt);
+      plan->adj_ckpt = nullptr;
+      return fail(SSFM_ENOMEM, "adjoint workspace of %zu bytes", ckpt_bytes + work_bytes);
+    }
+    plan->adj_ckpt_bytes = ckpt_bytes;
+    plan->adj_work_bytes = work_bytes;
+  }
+  float2* work = plan->adj_work;
+  float2* cot = work + slice;
+  // forward pass on a copy of the input, keeping the span-end states
+  if ((e = hipMemcpyAsync(work, field_in, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return fail_hip(e, "hipMemcpyAsync (adjoint input)");
+  rc = run_forward(plan, work, batch, seed, 0, 0, plan->spans, st, plan->adj_ckpt);
+  if (rc != SSFM_OK) return rc;
+  if ((e = hipMemcpyAsync(cot, grad, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return fail_hip(e, "hipMemcpyAsync (cotangent)");
+
+  // reverse sweep: state and cotangent together, span by span
+  const int64_t batch2 = 2 * batch;
+  bool wide = false;
+  (void)pick_cols(plan, batch2, &wide);
+  const ssfm::RowLaunch row = wide ? ks.row_wide : ks.row_narrow;
+  const int64_t rows = batch2 * plan->n_pol * ks.n1;
+  const double row_bytes = 2.0 * (double)batch2 * plan->n_pol * (double)plan->n * sizeof(float2);
+  int log2_n2 = 0;
+  while ((1 << log2_n2) < ks.n2) ++log2_n2;
+  ssfm::RowArgs ra{};
+  ra.field = work;
+  ra.tw = plan->tw2;
+  ra.twA = plan->twA;
+  ra.twB = plan->twB;
+  ra.n1 = ks.n1;
+  ra.log2_n2 = log2_n2;
+  ra.conj_h = 1;
+  ssfm::AdjArgs aa{};
+  aa.work = work;
+  aa.tw1 = plan->tw1;
+  aa.n2 = ks.n2;
+  aa.n = plan->n;
+  aa.batch = batch;
+  aa.gspan = plan->gspan;
+  for (int s = plan->spans - 1; s >= 0; --s) {
+    aa.ckpt = plan->adj_ckpt + (size_t)s * slice;
+    if ((e = launch(plan, KIND_ADJ, row_bytes, st,
+                    [&] { return ks.adj[ssfm::AMODE_FIRST](aa, st); })) != hipSuccess)
+      return fail_hip(e, "k3_adj launch");
+    for (int i = plan->steps; i >= 0; --i) {
+      ra.H = (i == 0 || i == plan->steps) ? plan->h_half : plan->h_full;
+      if ((e = launch(plan, KIND_ROW, row_bytes, st, [&] { return row(ra, rows, st); })) !=
+          hipSuccess)
+        return fail_hip(e, "k2 launch");
+      if (i > 0) {
+        aa.kappa = plan->kappa[(size_t)(i - 1)];
+        if ((e = launch(plan, KIND_ADJ, row_bytes, st,
+                        [&] { return ks.adj[ssfm::AMODE_NL](aa, st); })) != hipSuccess)
+          return fail_hip(e, "k3_adj launch");
+      }
+    }
+    if ((e = launch(plan, KIND_ADJ, row_bytes, st,
+                    [&] { return ks.adj[ssfm::AMODE_LAST](aa, st); })) != hipSuccess)
+      return fail_hip(e, "k3_adj launch");
+  }
+  if ((e = hipMemcpyAsync(grad, cot, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return fail_hip(e, "hipMemcpyAsync (gradient)");
+  return SSFM_OK;
 }
 
 int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
@@ -476,8 +569,8 @@ int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int
   if (!plan || !out || !count) return fail(SSFM_EINVAL, "plan, out and count must be non-NULL");
   plan->profiling = false;
   DeviceGuard guard(plan->device);
-  double ms[KIND_COUNT] = {0, 0, 0}, bytes[KIND_COUNT] = {0, 0, 0};
-  int64_t n[KIND_COUNT] = {0, 0, 0};
+  double ms[KIND_COUNT] = {0, 0, 0, 0}, bytes[KIND_COUNT] = {0, 0, 0, 0};
+  int64_t n[KIND_COUNT] = {0, 0, 0, 0};
   const size_t launches = plan->prof_kind.size();
   if (launches) {
     hipError_t e = hipEventSynchronize(plan->events[2 * launches - 1]);

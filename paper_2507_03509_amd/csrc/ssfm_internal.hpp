@@ -22,6 +22,7 @@ struct RowArgs {
   const cd* twB;     // W_N^{b}, b < N2
   int n1;
   int log2_n2;
+  int conj_h;        // 1: multiply by conj(H) (adjoint / inverse linear step)
 };
 
 struct ColArgs {
@@ -35,6 +36,26 @@ struct ColArgs {
   uint64_t seed;
   uint64_t realization0;
   int span;
+  float2* ckpt;      // MODE_EDFA/LAST: if set, the pre-amplifier time-domain
+                     // field is stored here ([batch][pol][n]), else unused
+};
+
+// adjoint column-pass variants (state = reconstructed forward field,
+// cotangent = dL/dA*), on a work buffer holding both: realisation b's state
+// at b, its cotangent at batch + b
+enum { AMODE_FIRST = 0,  // state <- checkpoint, both: time -> mixed
+       AMODE_NL = 1,     // both: mixed -> time, inverse step + pullback, -> mixed
+       AMODE_LAST = 2 }; // cotangent: mixed -> time, times the span gain
+
+struct AdjArgs {
+  float2* work;      // [2 batch][pol][n]
+  const float2* ckpt;  // AMODE_FIRST: span-end state [batch][pol][n]
+  const cd* tw1;
+  int n2;
+  int64_t n;
+  int64_t batch;
+  double kappa;      // AMODE_NL
+  double gspan;      // AMODE_LAST
 };
 
 struct LdsArgs {
@@ -54,6 +75,7 @@ struct LdsArgs {
 using RowLaunch = hipError_t (*)(const RowArgs&, int64_t, hipStream_t);
 using ColLaunch = hipError_t (*)(const ColArgs&, int64_t, hipStream_t);
 using LdsLaunch = hipError_t (*)(const LdsArgs&, int64_t, hipStream_t);
+using AdjLaunch = hipError_t (*)(const AdjArgs&, hipStream_t);
 
 struct FourStepKernels {
   ColLaunch col[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -69,6 +91,8 @@ struct KernelSet {
   int rows_wide = 0, rows_narrow = 0;  // rows per workgroup
   // column tiles: narrow (2 columns), mid, wide
   FourStepKernels narrow, mid, wide;
+  AdjLaunch adj[3] = {nullptr, nullptr, nullptr};
+  int adj_columns = 0;
   hipError_t prepare = hipSuccess;
 };
 

@@ -82,7 +82,7 @@ __device__ __forceinline__ cd four_step_twiddle(const cd* __restrict__ twA,
 // ---------------------------------------------------------------------------
 // K2: rows of length N2 (contiguous), WG lanes, FP32 LDS exchange.
 // ---------------------------------------------------------------------------
-template <int N2, int WG, typename L>
+template <int N2, int WG, typename L, bool CONJ>
 __global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field, const cd* __restrict__ H,
                                               const cd* __restrict__ tw,
                                               const cd* __restrict__ twA,
@@ -113,8 +113,9 @@ __global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field, const 
   }
   fft<N2, false, true, true>(reg, mylds, 1, j, tw);  // one wave per row
   const cd* hp = H + (int64_t)k1 * N2;
+  // CONJ: conj(H), the adjoint (and inverse) of the unitary linear step
 #pragma unroll
-  for (int r = 0; r < 16; ++r) reg[r] = cmul(reg[r], hp[j + T * r]);
+  for (int r = 0; r < 16; ++r) reg[r] = cmul_t<CONJ>(reg[r], hp[j + T * r]);
   fft<N2, true, true, true>(reg, mylds, 1, j, tw);
   {
     cd w = w0;
@@ -190,6 +191,12 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
       // unrolled one, so the field registers are never indexed at run time.
       const uint64_t key1 = (a.realization0 + (uint64_t)b) * 65536ull + (uint64_t)a.span;
       const bool noisy = a.sigma_h != 0.0;
+      if (a.ckpt) {
+        // span-end state before the amplifier, for the adjoint
+        float2* cp = a.ckpt + (b * P + p) * a.n + n2;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) store_c64(cp + (int64_t)(j + T * r) * a.n2, reg[r]);
+      }
       float2* nbuf = reinterpret_cast<float2*>(lds3_raw) + p * (N1 * C) + c;
       if (noisy) {
         __syncthreads();  // the inverse FFT's LDS reads are done
@@ -215,6 +222,97 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
   if constexpr (MODE != MODE_LAST) {
     // time -> mixed domain: column FFT
     fft<N1, false, false, false>(reg, mylds, C, j, a.tw1);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
+}
+
+// ---------------------------------------------------------------------------
+// K3 adjoint: column tiles of the work buffer holding, for realisation b, the
+// reconstructed forward state (at b) and the cotangent dL/dA* (at batch + b).
+// Lanes: field f (0 state, 1 cotangent) x polarisation x C columns x T.
+//   AMODE_FIRST  state <- span-end checkpoint; both fields time -> mixed
+//   AMODE_NL     both mixed -> time; with y the state (output of the forward
+//                nonlinear step) and phi = kappa sum_q |y_q|^2:
+//                  state     x   = y e^{-i phi}            (inverse step)
+//                  cotangent g_x = g_y e^{-i phi} + 2 s kappa x,
+//                            s   = -Im sum_q conj(g_y,q) y_q (pullback)
+//                then both time -> mixed
+//   AMODE_LAST   cotangent mixed -> time, times the span gain (the pullback of
+//                the amplifier, applied at the end of the span's reverse sweep
+//                because everything in between is linear in the cotangent)
+// ---------------------------------------------------------------------------
+template <int N1, int C, int P, int AMODE>
+__global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
+  constexpr int T = N1 / 16;
+  extern __shared__ __align__(16) unsigned char lds_adj[];
+  cd* lds = reinterpret_cast<cd*>(lds_adj);
+  const int tid = threadIdx.x;
+  const int f = tid / (P * C * T);
+  const int rem0 = tid % (P * C * T);
+  const int p = rem0 / (C * T);
+  const int rem = rem0 % (C * T);
+  const int c = rem % C;
+  const int j = rem / C;
+  const int tiles = a.n2 / C;
+  const unsigned G = gridDim.x;
+  const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int64_t b = id / tiles;
+  const int n2 = (int)(id % tiles) * C + c;
+  float2* fp = a.work + ((f * a.batch + b) * P + p) * a.n + n2;
+  cd* mylds = lds + (f * P + p) * (N1 * C) + c;
+  const float2* src = fp;
+  if constexpr (AMODE == AMODE_FIRST) {
+    if (f == 0) src = a.ckpt + (b * P + p) * a.n + n2;
+  }
+  cd reg[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) reg[r] = load_c64(src + (int64_t)(j + T * r) * a.n2);
+
+  if constexpr (AMODE == AMODE_FIRST) {
+    fft<N1, false, false, false>(reg, mylds, C, j, a.tw1);
+  } else if constexpr (AMODE == AMODE_NL) {
+    fft<N1, true, false, false>(reg, mylds, C, j, a.tw1);
+    __syncthreads();  // the inverse FFT's LDS reads are done
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds[((f * P + p) * N1 + j + T * r) * C + c] = reg[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = (j + T * r) * C + c;
+      double pw = 0.0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const cd yq = lds[q * N1 * C + i];
+        pw = fma(yq.re, yq.re, fma(yq.im, yq.im, pw));
+      }
+      const cd e = unit_phasor(-a.kappa * pw);  // e^{-i phi}
+      const cd yp = lds[p * N1 * C + i];
+      const cd x = cmul(yp, e);
+      if (f == 0) {
+        reg[r] = x;
+      } else {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const cd yq = lds[q * N1 * C + i];
+          const cd gq = lds[(P + q) * N1 * C + i];
+          s -= fma(gq.re, yq.im, -gq.im * yq.re);  // -Im(conj(g) y)
+        }
+        const cd gx = cmul(reg[r], e);
+        const double w = 2.0 * s * a.kappa;
+        reg[r] = {fma(w, x.re, gx.re), fma(w, x.im, gx.im)};
+      }
+    }
+    fft<N1, false, false, false>(reg, mylds, C, j, a.tw1);
+  }
+  if constexpr (AMODE == AMODE_LAST) {
+    // every lane transforms (the block barriers need all of them); only the
+    // cotangent is stored, the state is not needed past the span start
+    fft<N1, true, false, false>(reg, mylds, C, j, a.tw1);
+    if (f == 0) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) reg[r] = round_c64(cscale(reg[r], a.gspan));
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
@@ -307,8 +405,12 @@ static hipError_t launch_k2(const RowArgs& a, int64_t rows, hipStream_t st) {
   constexpr int T = N2 / 16;
   constexpr int RPW = WG / T;
   const size_t lds = (size_t)RPW * (N2 + N2 / 16) * sizeof(L);
-  hipLaunchKernelGGL((k2_rows<N2, WG, L>), dim3((unsigned)(rows / RPW)), dim3(WG), lds, st,
-                     a.field, a.H, a.tw, a.twA, a.twB, a.n1, a.log2_n2);
+  if (a.conj_h)
+    hipLaunchKernelGGL((k2_rows<N2, WG, L, true>), dim3((unsigned)(rows / RPW)), dim3(WG), lds,
+                       st, a.field, a.H, a.tw, a.twA, a.twB, a.n1, a.log2_n2);
+  else
+    hipLaunchKernelGGL((k2_rows<N2, WG, L, false>), dim3((unsigned)(rows / RPW)), dim3(WG), lds,
+                       st, a.field, a.H, a.tw, a.twA, a.twB, a.n1, a.log2_n2);
   return hipGetLastError();
 }
 
@@ -316,10 +418,12 @@ template <int N2, int WG, typename L>
 static hipError_t prepare_k2() {
   constexpr int T = N2 / 16;
   const size_t lds = (size_t)(WG / T) * (N2 + N2 / 16) * sizeof(L);
-  if (lds > 65536)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_rows<N2, WG, L>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return hipSuccess;
+  if (lds <= 65536) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_rows<N2, WG, L, false>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_rows<N2, WG, L, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <int N1, int C, int P, int MODE, typename L>
@@ -367,6 +471,38 @@ static hipError_t prepare_k3_one() {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_cols<N1, C, P, MODE, L>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   return hipSuccess;
+}
+
+template <int N1, int C, int P, int AMODE>
+static hipError_t launch_k3_adj(const AdjArgs& a, hipStream_t st) {
+  constexpr int T = N1 / 16;
+  const size_t lds = (size_t)2 * P * C * N1 * sizeof(cd);
+  const unsigned blocks = (unsigned)(a.batch * (a.n2 / C));
+  hipLaunchKernelGGL((k3_adj<N1, C, P, AMODE>), dim3(blocks), dim3(2 * P * C * T), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int N1, int C, int P, int AMODE>
+static hipError_t prepare_k3_adj() {
+  const size_t lds = (size_t)2 * P * C * N1 * sizeof(cd);
+  if (lds > 65536)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_adj<N1, C, P, AMODE>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
+// adjoint column tiles: 4 columns (2 at N1 = 512), both fields, FP64 LDS
+// (64 KB per workgroup)
+template <int N1, int P>
+static void fill_adj(KernelSet& ks) {
+  constexpr int C = N1 == 512 ? 2 : 4;
+  ks.adj[AMODE_FIRST] = &launch_k3_adj<N1, C, P, AMODE_FIRST>;
+  ks.adj[AMODE_NL] = &launch_k3_adj<N1, C, P, AMODE_NL>;
+  ks.adj[AMODE_LAST] = &launch_k3_adj<N1, C, P, AMODE_LAST>;
+  ks.adj_columns = C;
+  for (hipError_t e : {prepare_k3_adj<N1, C, P, AMODE_FIRST>(), prepare_k3_adj<N1, C, P, AMODE_NL>(),
+                       prepare_k3_adj<N1, C, P, AMODE_LAST>()})
+    if (e != hipSuccess) ks.prepare = e;
 }
 
 // ---- dispatch tables ------------------------------------------------------
@@ -436,9 +572,18 @@ bool select_kernels(int64_t n, int n_pol, KernelSet& ks) {
   }
   if (pr != hipSuccess) ks.prepare = pr;
   switch (ks.n1) {
-    case 128: if (n_pol == 1) fill_cols<128, 1>(ks); else fill_cols<128, 2>(ks); break;
-    case 256: if (n_pol == 1) fill_cols<256, 1>(ks); else fill_cols<256, 2>(ks); break;
-    case 512: if (n_pol == 1) fill_cols<512, 1>(ks); else fill_cols<512, 2>(ks); break;
+    case 128:
+      if (n_pol == 1) { fill_cols<128, 1>(ks); fill_adj<128, 1>(ks); }
+      else { fill_cols<128, 2>(ks); fill_adj<128, 2>(ks); }
+      break;
+    case 256:
+      if (n_pol == 1) { fill_cols<256, 1>(ks); fill_adj<256, 1>(ks); }
+      else { fill_cols<256, 2>(ks); fill_adj<256, 2>(ks); }
+      break;
+    case 512:
+      if (n_pol == 1) { fill_cols<512, 1>(ks); fill_adj<512, 1>(ks); }
+      else { fill_cols<512, 2>(ks); fill_adj<512, 2>(ks); }
+      break;
     default: return false;
   }
   for (const FourStepKernels* k : {&ks.wide, &ks.mid, &ks.narrow})

@@ -1,0 +1,107 @@
+"""GPU adjoint (ssfm_adjoint through the C ABI, and the autograd wrapper)
+against the FP64 oracle's adjoint, whose pins are in test_oracle_adjoint."""
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from workloads import CONFIGS, Link, dual_pol_field, make_field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_03509_amd as m
+    m.load_library()
+    return m
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def link(n_pol, n, spans, steps, **kw):
+    base = dict(n_pol=n_pol, n_samples=n, sample_rate_hz=128e9, span_km=80.0, n_spans=spans,
+                steps_per_span=steps, alpha_db_per_km=0.2, beta2_ps2_per_km=-21.7,
+                gamma_per_w_km=1.3, edfa_gain_db=16.0, edfa_nf_db=5.0, ase=True)
+    base.update(kw)
+    return Link(**base)
+
+
+def gpu_adjoint(ssfm, x, g, ln, seed):
+    xt = torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).cuda()
+    gt = torch.from_numpy(np.ascontiguousarray(g, dtype=np.complex64)).cuda()
+    plan = ssfm.Plan(ln)
+    try:
+        plan.adjoint(xt, gt, seed=seed)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    return gt.cpu().numpy().astype(np.complex128), xt.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,n_pol", [(1 << 14, 2), (1 << 14, 1), (1 << 16, 2), (1 << 18, 2)])
+def test_adjoint_matches_oracle(ssfm, n, n_pol):
+    print(f"case n={n} n_pol={n_pol}", flush=True)
+    rng = np.random.default_rng(n + n_pol)
+    ln = link(n_pol, n, spans=2, steps=5)
+    b = 2
+    x = np.stack([dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 6.0) for _ in range(b)])
+    g = np.stack([dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 0.0) for _ in range(b)])
+    got, x_after = gpu_adjoint(ssfm, x, g, ln, seed=21)
+    assert np.array_equal(x_after, x.astype(np.complex64))  # input untouched
+    for r in range(b):
+        want = oracle.adjoint(x[r], g[r], ln, seed=21, realization=r)
+        assert rel(got[r], want) < 1e-5, (r, rel(got[r], want))
+
+
+def test_adjoint_workload2_full_link(ssfm):
+    w = CONFIGS[2]
+    x = make_field(w)
+    rng = np.random.default_rng(5)
+    g = dual_pol_field(rng, 2, w.link.n_samples, 2, 64e9, 0.1, 0.0)
+    got, _ = gpu_adjoint(ssfm, x[None], g[None], w.link, seed=w.ase_seed)
+    want = oracle.adjoint(x, g, w.link, seed=w.ase_seed)
+    err = rel(got[0], want)
+    print(f"workload2 adjoint rel_err={err:.3e}", flush=True)
+    assert err < 1e-5
+
+
+def test_autograd_mse_gradient(ssfm):
+    n = 1 << 14
+    ln = link(2, n, spans=2, steps=4)
+    rng = np.random.default_rng(17)
+    x0 = dual_pol_field(rng, 2, n, 2, 64e9, 0.1, 4.0)
+    target = dual_pol_field(rng, 2, n, 2, 64e9, 0.1, 4.0)
+    plan = ssfm.Plan(ln)
+    x = torch.from_numpy(x0.astype(np.complex64))[None].cuda().requires_grad_(True)
+    t = torch.from_numpy(target.astype(np.complex64))[None].cuda()
+    y = ssfm.propagate(x, plan, seed=3)
+    loss = torch.mean(torch.abs(y - t) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    # dL/dy* = (y - t) / numel; PyTorch's complex gradient is 2 dL/dz*
+    y_np = y.detach().cpu().numpy().astype(np.complex128)[0]
+    gy = (y_np - target) / y_np.size
+    want = 2 * oracle.adjoint(x0, gy, ln, seed=3)
+    got = x.grad.detach().cpu().numpy().astype(np.complex128)[0]
+    assert rel(got, want) < 1e-5
+    plan.close()
+
+
+def test_adjoint_rejects_lds_path(ssfm):
+    ln = link(2, 4096, spans=1, steps=2)
+    x = torch.zeros((1, 2, 4096), dtype=torch.complex64, device="cuda")
+    g = torch.zeros_like(x)
+    plan = ssfm.Plan(ln)
+    with pytest.raises(ssfm.SsfmError) as e:
+        plan.adjoint(x, g)
+    assert e.value.status == ssfm.SSFM_EUNSUPPORTED
+    plan.close()
