@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=512)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4],
+                    help="2: Manakov 2^16 link over a batch; 4: 256 mixed realisations "
+                         "(ssfm_batch against the one-at-a-time loop)")
     ap.add_argument("--single-steps", type=int, default=3,
                     help="timed calls of the batch-1 figure (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -81,8 +83,81 @@ def traffic_record(kernel: str):
     return ent
 
 
+def bench_mixed_batch(args) -> int:
+    """Workload 4: 256 independent dual-pol realisations with lengths drawn
+    from 2^12..2^16, launch power in [-4, +6] dBm, 1..10 spans of 50 steps and
+    distinct seeds -- one ssfm_batch call against one ssfm_forward call per
+    realisation."""
+    import numpy as np
+    import torch
+
+    import paper_2507_03509_amd as ssfm
+    from workloads import batch_config, dual_pol_field
+
+    ssfm.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    items = batch_config(256)
+    rng = np.random.default_rng(20250703 + 44)
+    links = [it.link() for it in items]
+    inputs = [dual_pol_field(rng, 2, ln.n_samples, 2, 64e9, 0.1, it.launch_dbm)
+              for it, ln in zip(items, links)]
+    seeds = [it.seed for it in items]
+    fields = [torch.from_numpy(a.astype(np.complex64)).to(dev) for a in inputs]
+    work = sum(ln.n_samples * ln.n_spans * ln.steps_per_span for ln in links)
+    stream = torch.cuda.current_stream(dev)
+    log(f"workload 4: {len(items)} realisations, {work:.3e} sample-steps per pass")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_batch = timed(lambda: ssfm.ssfm_batch(links, fields, seeds, 0, stream), args.steps)
+    plans = {}
+    for ln in links:
+        key = (ln.n_samples,)
+        if key not in plans:
+            plans[key] = ssfm.Plan(ln.replace(n_spans=10), device=0)
+
+    def loop():
+        for ln, f, sd in zip(links, fields, seeds):
+            plans[(ln.n_samples,)].forward(f, seed=sd, span_end=ln.n_spans, stream=stream)
+
+    ms_loop = timed(loop, max(1, args.steps // 2))
+    value = work / (ms_batch / 1e3)
+    loop_rate = work / (ms_loop / 1e3)
+    log(f"ssfm_batch: {ms_batch:.2f} ms per pass ({value:.4e} sample-steps/s); "
+        f"one-at-a-time: {ms_loop:.2f} ms ({loop_rate:.4e}); speedup {ms_loop / ms_batch:.2f}x")
+    out = {
+        "metric": METRIC, "value": value, "unit": "sample-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(ms_batch, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "mixed batch: 256 dual-pol realisations, 2^12..2^16 samples, "
+                               "1..10 x 80 km spans of 50 steps, -4..+6 dBm, distinct seeds",
+                   "sample_steps_per_pass": work, "parallelism": "single-gpu"},
+        "one_at_a_time": {"ms_per_pass": round(ms_loop, 3), "sample_steps_per_s": loop_rate},
+        "batched_speedup": round(ms_loop / ms_batch, 3),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    for pl in plans.values():
+        pl.close()
+    return 0
+
+
 def main() -> int:
     args = parse()
+    if args.workload == 4 and args.gpus == 1:
+        return bench_mixed_batch(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the SSFM "
               "path has no multi-GPU code", file=sys.stderr)

@@ -150,9 +150,19 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
 int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
                  int64_t batch, uint64_t seed, void* stream);
 
-/* Independent realisations of different lengths, launch powers and span
- * counts in one call.  Not implemented in this build: returns
- * SSFM_EUNSUPPORTED after argument validation. */
+/* Independent realisations of different links in one call: entry i (of
+ * `count`) propagates the device field fields[i] (complex64
+ * [links[i].n_pol][links[i].n_samples], in place) through links[i] with
+ * noise key (seeds[i], span) -- the key ssfm_forward uses for seed seeds[i]
+ * and realisation 0.  Lengths, span counts, launch powers (the fields'
+ * content) and seeds may all differ.  Entries whose links agree in
+ * everything but the span count are propagated together: gathered into one
+ * stream-ordered staging buffer, most spans first, and run over span
+ * segments on the shrinking prefix of entries still propagating; plans are
+ * built on first use and cached for the life of the process.  links, fields
+ * and seeds are host arrays; the call is asynchronous on `stream` of device
+ * `hip_device`.  Errors: SSFM_EINVAL (invalid link, NULL or misaligned
+ * pointer, count < 1), SSFM_ENOMEM, SSFM_EHIP. */
 int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
                const uint64_t* seeds, int hip_device, void* stream);
 

@@ -6,6 +6,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -279,7 +283,8 @@ const ssfm::FourStepKernels& pick_cols(const ssfm_plan_s* p, int64_t batch, bool
 }
 
 int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uint64_t real0,
-                int s0, int s1, hipStream_t st, float2* ckpt = nullptr) {
+                int s0, int s1, hipStream_t st, float2* ckpt = nullptr,
+                const uint64_t* seeds = nullptr) {
   const ssfm::KernelSet& ks = p->ks;
   hipError_t e;
   if (s0 == s1) return SSFM_OK;
@@ -299,6 +304,7 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
     a.sigma_h = p->sigma_h;
     a.seed = seed;
     a.realization0 = real0;
+    a.seeds = seeds;
     if ((e = launch(p, KIND_LDS, field_bytes, st, [&] { return ks.lds(a, batch, st); })) != hipSuccess)
       return fail_hip(e, "k1_lds launch");
     return SSFM_OK;
@@ -326,6 +332,7 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
   a.sigma_h = p->sigma_h;
   a.seed = seed;
   a.realization0 = real0;
+  a.seeds = seeds;
   if ((e = launch(p, KIND_COL, field_bytes, st,
                   [&] { return cols.col[ssfm::MODE_FIRST](a, batch, st); })) != hipSuccess)
     return fail_hip(e, "k3 launch");
@@ -364,6 +371,55 @@ int check_call(ssfm_plan_t plan, const void* field, int64_t batch) {
   return SSFM_OK;
 }
 
+constexpr int kMaxSpans = 65535;
+
+bool same_double(double a, double b) {
+  return (isnan(a) && isnan(b)) || memcmp(&a, &b, sizeof a) == 0;
+}
+
+bool same_link(const ssfm_link& a, const ssfm_link& b) {
+  return a.n_pol == b.n_pol && a.n_spans == b.n_spans && a.steps_per_span == b.steps_per_span &&
+         a.ase == b.ase && a.n_samples == b.n_samples &&
+         same_double(a.sample_rate_hz, b.sample_rate_hz) && same_double(a.span_km, b.span_km) &&
+         same_double(a.alpha_db_per_km, b.alpha_db_per_km) &&
+         same_double(a.beta2_ps2_per_km, b.beta2_ps2_per_km) &&
+         same_double(a.gamma_per_w_km, b.gamma_per_w_km) &&
+         same_double(a.nl_factor, b.nl_factor) && same_double(a.edfa_gain_db, b.edfa_gain_db) &&
+         same_double(a.edfa_nf_db, b.edfa_nf_db) && same_double(a.carrier_hz, b.carrier_hz) &&
+         a.flags == b.flags && a.reserved == b.reserved;
+}
+
+// Plans built by ssfm_batch, kept for the life of the process (one per
+// distinct link and device).
+struct PlanCache {
+  std::mutex mu;
+  std::vector<std::pair<std::pair<ssfm_link, int>, ssfm_plan_t>> plans;
+};
+PlanCache& plan_cache() {
+  static PlanCache* c = new PlanCache();  // never destroyed: plans outlive static teardown
+  return *c;
+}
+
+}  // namespace
+
+extern "C" int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out);
+
+namespace {
+int cached_plan(const ssfm_link& key, int device, ssfm_plan_t* out) {
+  PlanCache& c = plan_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  for (auto& e : c.plans)
+    if (e.first.second == device && same_link(e.first.first, key)) {
+      *out = e.second;
+      return SSFM_OK;
+    }
+  ssfm_plan_t p = nullptr;
+  const int rc = ssfm_plan(&key, device, &p);
+  if (rc != SSFM_OK) return rc;
+  c.plans.push_back({{key, device}, p});
+  *out = p;
+  return SSFM_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -543,8 +599,6 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
 
 int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
                const uint64_t* seeds, int hip_device, void* stream) {
-  (void)hip_device;
-  (void)stream;
   g_last_error.clear();
   if (!links || !fields || !seeds) return fail(SSFM_EINVAL, "links, fields and seeds must be non-NULL");
   if (count < 1) return fail(SSFM_EINVAL, "count must be >= 1");
@@ -552,8 +606,84 @@ int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
     int rc = validate_link(&links[i]);
     if (rc != SSFM_OK) return rc;
     if (!fields[i]) return fail(SSFM_EINVAL, "fields[%lld] is NULL", (long long)i);
+    if (((uintptr_t)fields[i] & 7u) != 0)
+      return fail(SSFM_EINVAL, "fields[%lld] must be 8-byte aligned", (long long)i);
   }
-  return fail(SSFM_EUNSUPPORTED, "ssfm_batch is not implemented in this build");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceCount");
+  if (hip_device < 0 || hip_device >= ndev)
+    return fail(SSFM_EINVAL, "hip_device %d out of range (%d devices)", hip_device, ndev);
+  DeviceGuard guard(hip_device);
+  if (guard.status != hipSuccess) return fail_hip(guard.status, "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // group by physical link (the span count is per entry: plans do not depend
+  // on it), keeping first-seen order
+  std::vector<std::vector<int64_t>> groups;
+  std::vector<ssfm_link> keys;
+  for (int64_t i = 0; i < count; ++i) {
+    ssfm_link k = links[i];
+    k.n_spans = kMaxSpans;
+    size_t gi = 0;
+    while (gi < keys.size() && !same_link(keys[gi], k)) ++gi;
+    if (gi == keys.size()) {
+      keys.push_back(k);
+      groups.emplace_back();
+    }
+    groups[gi].push_back(i);
+  }
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    ssfm_plan_t plan = nullptr;
+    int rc = cached_plan(keys[gi], hip_device, &plan);
+    if (rc != SSFM_OK) return rc;
+    std::vector<int64_t>& idx = groups[gi];
+    // most spans first: the realisations still propagating are a prefix
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      return links[a].n_spans > links[b].n_spans;
+    });
+    const int64_t m = (int64_t)idx.size();
+    const size_t elems = (size_t)plan->n_pol * plan->n;
+    const size_t fbytes = elems * sizeof(float2);
+    void* stage = nullptr;
+    void* dseeds = nullptr;
+    if ((e = hipMallocAsync(&stage, (size_t)m * fbytes, st)) != hipSuccess)
+      return fail(SSFM_ENOMEM, "staging buffer of %zu bytes: %s", (size_t)m * fbytes,
+                  hipGetErrorString(e));
+    if ((e = hipMallocAsync(&dseeds, (size_t)m * sizeof(uint64_t), st)) != hipSuccess) {
+      (void)hipFreeAsync(stage, st);
+      return fail(SSFM_ENOMEM, "seed buffer: %s", hipGetErrorString(e));
+    }
+    std::vector<uint64_t> hseeds((size_t)m);
+    for (int64_t r = 0; r < m; ++r) {
+      hseeds[(size_t)r] = seeds[idx[(size_t)r]];
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(static_cast<float2*>(stage) + (size_t)r * elems, fields[idx[(size_t)r]],
+                           fbytes, hipMemcpyDeviceToDevice, st);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dseeds, hseeds.data(), (size_t)m * sizeof(uint64_t),
+                         hipMemcpyHostToDevice, st);
+    // segments of constant active count
+    int s0 = 0;
+    while (rc == SSFM_OK && e == hipSuccess) {
+      int64_t active = 0;
+      while (active < m && links[idx[(size_t)active]].n_spans > s0) ++active;
+      if (active == 0) break;
+      const int s1 = links[idx[(size_t)(active - 1)]].n_spans;
+      rc = run_forward(plan, static_cast<float2*>(stage), active, 0, 0, s0, s1, st, nullptr,
+                       static_cast<const uint64_t*>(dseeds));
+      s0 = s1;
+    }
+    for (int64_t r = 0; r < m && rc == SSFM_OK && e == hipSuccess; ++r)
+      e = hipMemcpyAsync(fields[idx[(size_t)r]], static_cast<float2*>(stage) + (size_t)r * elems,
+                         fbytes, hipMemcpyDeviceToDevice, st);
+    (void)hipFreeAsync(stage, st);
+    (void)hipFreeAsync(dseeds, st);
+    if (rc != SSFM_OK) return rc;
+    if (e != hipSuccess) return fail_hip(e, "ssfm_batch copies");
+  }
+  return SSFM_OK;
 }
 
 int ssfm_profile_begin(ssfm_plan_t plan) {

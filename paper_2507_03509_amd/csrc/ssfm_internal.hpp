@@ -38,6 +38,8 @@ struct ColArgs {
   int span;
   float2* ckpt;      // MODE_EDFA/LAST: if set, the pre-amplifier time-domain
                      // field is stored here ([batch][pol][n]), else unused
+  const uint64_t* seeds;  // if set, realisation b's noise key is
+                          // (seeds[b], span), else (seed, (realization0 + b) 2^16 + span)
 };
 
 // adjoint column-pass variants (state = reconstructed forward field,
@@ -70,6 +72,7 @@ struct LdsArgs {
   double sigma_h;
   uint64_t seed;
   uint64_t realization0;
+  const uint64_t* seeds;  // as ColArgs::seeds
 };
 
 using RowLaunch = hipError_t (*)(const RowArgs&, int64_t, hipStream_t);

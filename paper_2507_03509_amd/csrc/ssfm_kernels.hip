@@ -189,7 +189,9 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
       // amplifier: a <- gspan a + ASE(t), t = n1 N2 + n2.  The noise is drawn
       // in a rolled loop into this lane's own LDS slots and added back in an
       // unrolled one, so the field registers are never indexed at run time.
-      const uint64_t key1 = (a.realization0 + (uint64_t)b) * 65536ull + (uint64_t)a.span;
+      const uint64_t key0 = a.seeds ? a.seeds[b] : a.seed;
+      const uint64_t key1 = a.seeds ? (uint64_t)a.span
+                                    : (a.realization0 + (uint64_t)b) * 65536ull + (uint64_t)a.span;
       const bool noisy = a.sigma_h != 0.0;
       if (a.ckpt) {
         // span-end state before the amplifier, for the adjoint
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
 #pragma unroll 1
         for (int r = 0; r < 16; ++r) {
           const uint64_t t = (uint64_t)(j + T * r) * (uint64_t)a.n2 + (uint64_t)n2;
-          const u64x4 w = philox4x64_10(t, 0, 0, 0, a.seed, key1);
+          const u64x4 w = philox4x64_10(t, 0, 0, 0, key0, key1);
           nbuf[(j + T * r) * C] = p == 0 ? box_muller(w.w[0], w.w[1]) : box_muller(w.w[2], w.w[3]);
         }
       }
@@ -339,7 +341,8 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) reg[q][r] = load_c64(fp + q * N + jj + T * r);
 
-  const uint64_t rkey = (a.realization0 + (uint64_t)b) * 65536ull;
+  const uint64_t key0 = a.seeds ? a.seeds[b] : a.seed;
+  const uint64_t rkey = a.seeds ? 0ull : (a.realization0 + (uint64_t)b) * 65536ull;
   for (int s = a.span_begin; s < a.span_end; ++s) {
     for (int i = 0; i <= a.steps; ++i) {
       if (i > 0) {
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
       __syncthreads();  // the inverse FFT's LDS reads are done
 #pragma unroll 1
       for (int r = 0; r < 16; ++r) {
-        const u64x4 w = philox4x64_10((uint64_t)(jj + T * r), 0, 0, 0, a.seed, rkey + (uint64_t)s);
+        const u64x4 w = philox4x64_10((uint64_t)(jj + T * r), 0, 0, 0, key0, rkey + (uint64_t)s);
         nbuf[jj + T * r] = box_muller(w.w[0], w.w[1]);
         if (P == 2) nbuf[N + jj + T * r] = box_muller(w.w[2], w.w[3]);
       }

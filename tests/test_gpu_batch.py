@@ -1,0 +1,89 @@
+"""ssfm_batch: independent realisations of different lengths, span counts,
+launch powers and seeds in one call, against the FP64 oracle and against
+one-at-a-time ssfm_forward."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from workloads import Link, batch_config, dual_pol_field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_03509_amd as m
+    m.load_library()
+    return m
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def entries(n_entries, steps, seed=0):
+    rng = np.random.default_rng(seed)
+    lengths = [1 << 12, 1 << 13, 1 << 14, 1 << 15, 1 << 16]
+    out = []
+    for i in range(n_entries):
+        n = lengths[i % len(lengths)]
+        spans = 1 + (i * 7) % 3
+        p_dbm = -4 + 10 * rng.random()
+        ln = Link(n_pol=2, n_samples=n, sample_rate_hz=128e9, span_km=80.0, n_spans=spans,
+                  steps_per_span=steps, alpha_db_per_km=0.2, beta2_ps2_per_km=-21.7,
+                  gamma_per_w_km=1.3, edfa_gain_db=16.0, edfa_nf_db=5.0, ase=True)
+        a = dual_pol_field(rng, 2, n, 2, 64e9, 0.1, p_dbm)
+        out.append((ln, a, 1000 + 17 * i))
+    return out
+
+
+def test_batch_matches_oracle_and_single_calls(ssfm):
+    es = entries(13, steps=5)
+    fields = [torch.from_numpy(a.astype(np.complex64)).cuda() for _, a, _ in es]
+    singles = [f.clone() for f in fields]
+    ssfm.ssfm_batch([ln for ln, _, _ in es], fields, [s for _, _, s in es], 0)
+    torch.cuda.synchronize()
+    for (ln, a, s), f, g in zip(es, fields, singles):
+        plan = ssfm.Plan(ln)
+        plan.forward(g, seed=s)
+        torch.cuda.synchronize()
+        plan.close()
+        got = f.cpu().numpy().astype(np.complex128)
+        want = oracle.propagate(a, ln, seed=s, realization=0)
+        assert rel(got, want) < 2e-6, (ln.n_samples, ln.n_spans, rel(got, want))
+        assert rel(got, g.cpu().numpy().astype(np.complex128)) < 1e-6
+
+
+def test_batch_workload4_shapes_run(ssfm):
+    # the workload-4 recipe (lengths 2^12..2^16, 1..10 spans, -4..+6 dBm,
+    # distinct seeds) at reduced count and steps; spot-check against the oracle
+    items = batch_config(n=24)
+    rng = np.random.default_rng(11)
+    links, fields, seeds, inputs = [], [], [], []
+    for it in items:
+        ln = it.link().replace(steps_per_span=4)
+        a = dual_pol_field(rng, 2, ln.n_samples, 2, 64e9, 0.1, it.launch_dbm)
+        links.append(ln)
+        inputs.append(a)
+        fields.append(torch.from_numpy(a.astype(np.complex64)).cuda())
+        seeds.append(it.seed)
+    ssfm.ssfm_batch(links, fields, seeds, 0)
+    torch.cuda.synchronize()
+    for k in (0, 5, 17):
+        want = oracle.propagate(inputs[k], links[k], seed=seeds[k], realization=0)
+        assert rel(fields[k].cpu().numpy().astype(np.complex128), want) < 2e-6
+
+
+def test_batch_rejects_invalid_entries(ssfm):
+    ln = Link(n_pol=2, n_samples=1000, sample_rate_hz=128e9, span_km=80.0, n_spans=1,
+              steps_per_span=2, alpha_db_per_km=0.2, beta2_ps2_per_km=-21.7,
+              gamma_per_w_km=1.3)
+    f = torch.zeros((2, 1024), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ssfm.SsfmError) as e:
+        ssfm.ssfm_batch([ln], [f], [1], 0)
+    assert e.value.status == ssfm.SSFM_EINVAL
