@@ -272,6 +272,9 @@ def main() -> int:
     single = None
     if args.single_steps > 0 and batch > 1:
         f1 = field[:1].clone()
+        # two untimed calls: the second identical call captures the launch
+        # sequence that the timed calls replay
+        plan.forward(f1, seed=w.ase_seed, stream=stream)
         plan.forward(f1, seed=w.ase_seed, stream=stream)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
