@@ -264,6 +264,13 @@ def main() -> int:
         a1.record(stream)
         torch.cuda.synchronize()
         ms_adj = a0.elapsed_time(a1)
+        # per-kernel breakdown of one more call (events around every launch)
+        ssfm.ssfm_profile_begin(plan.handle)
+        plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
+        torch.cuda.synchronize()
+        for s_ in ssfm.ssfm_profile_end(plan.handle):
+            log(f"  adjoint call {s_['name']}: {s_['launches']} launches, {s_['total_ms']:.1f} ms, "
+                f"{s_['field_bytes'] / (s_['total_ms'] * 1e-3) / 1e9:.1f} GB/s algorithmic")
         adj = {"fwd_adjoint_ms": round(ms_adj, 3), "ratio_to_forward": round(ms_adj / ms_per_step, 3)}
         log(f"forward+adjoint: {ms_adj:.3f} ms ({ms_adj / ms_per_step:.2f}x forward)")
         del grad

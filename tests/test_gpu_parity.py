@@ -229,3 +229,15 @@ def test_workload3_two_spans(ssfm):
     err = rel(got, want)
     print(f"workload3[2 spans] rel_err={err:.3e}", flush=True)
     assert err < TOL
+
+
+def test_workload3_full(ssfm):
+    # the full 20-span, 4000-step WDM link: the FP64 oracle takes tens of
+    # seconds on a fast host core
+    w = CONFIGS[3]
+    a0 = make_field(w)
+    got = run_gpu(ssfm, a0[None], w.link, seed=w.ase_seed)[0]
+    want = oracle.propagate(a0, w.link, seed=w.ase_seed)
+    err = rel(got, want)
+    print(f"workload3 rel_err={err:.3e}", flush=True)
+    assert err < TOL
