@@ -67,6 +67,25 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+# translation unit and headers each kernel is compiled from
+KERNEL_SOURCES = {
+    "k3_adj": ("ssfm_adjoint_kernels.hip",),
+}
+FORWARD_SOURCES = ("ssfm_kernels.hip", "philox_dev.hpp")
+SHARED_SOURCES = ("fft_dev.hpp", "kernel_common.hpp", "ssfm_internal.hpp")
+
+
+def kernel_source_digest(kernel: str) -> str:
+    """sha256 over the sources the kernel is built from: a traffic figure
+    counts only for the code it was measured on."""
+    csrc = os.path.join(ROOT, "paper_2507_03509_amd", "csrc")
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES.get(kernel, FORWARD_SOURCES) + SHARED_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_record(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source (else None)."""
@@ -75,8 +94,7 @@ def traffic_record(kernel: str):
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    src = os.path.join(ROOT, "paper_2507_03509_amd", "csrc", "ssfm_kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    digest = kernel_source_digest(kernel)
     ent = rec.get(kernel)
     if not ent or ent.get("kernel_source_sha256") != digest:
         return None

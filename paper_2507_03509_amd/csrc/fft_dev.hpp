@@ -215,16 +215,19 @@ __device__ __forceinline__ cd lds_get(const float2* p) {
   return {(double)v.x, (double)v.y};
 }
 
-// LDS slot of element i.  Contiguous transforms (ls = 1) get one pad slot per
-// 16 elements: the first pass writes with a stride of 16 elements, which
-// would otherwise put every lane of a row on the same bank.
-template <bool PAD>
+// LDS slot of element i.  The first pass writes with a stride of 16
+// elements.  PAD = 1: contiguous transforms (ls = 1) get one pad slot per 16
+// elements, else every lane of a row would hit the same bank.  PAD = 2:
+// interleaved transforms (element i of transform c at i ls + c) get one pad
+// row per 16, for tiles of ls < 8 FP64 columns where the lanes of one LDS
+// access group would otherwise span two rows a multiple of 1 KiB apart.
+template <int PAD>
 __device__ __forceinline__ int lds_slot(int i, int ls) {
-  return PAD ? i + (i >> 4) : i * ls;
+  return PAD == 1 ? i + (i >> 4) : PAD == 2 ? (i + (i >> 4)) * ls : i * ls;
 }
 
 // Read the inputs of pass P from LDS into the registers.
-template <int M, int P, bool PAD, typename L>
+template <int M, int P, int PAD, typename L>
 __device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, int j) {
   using S = fft_shape<M>;
   constexpr int R = S::radix(P);
@@ -240,7 +243,7 @@ __device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, i
 
 // Twiddle, butterfly and write of pass P.  DST_REG: the outputs stay in the
 // registers (last pass), otherwise they are written to LDS.
-template <int M, int P, bool INV, bool DST_REG, bool PAD, typename L>
+template <int M, int P, bool INV, bool DST_REG, int PAD, typename L>
 __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int j,
                                              const cd* __restrict__ tw) {
   using S = fft_shape<M>;
@@ -280,7 +283,7 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
   }
 }
 
-template <int M, bool INV, int P, int NT, bool PAD, bool WAVE, typename L>
+template <int M, bool INV, int P, int NT, int PAD, bool WAVE, typename L>
 __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride, int ls,
                                          int j, const cd* __restrict__ tw) {
   using S = fft_shape<M>;
@@ -302,11 +305,11 @@ __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride,
 // Lane j holds elements j + (M/16) r of each transform on entry and on exit.
 // Forward uses exp(-2 pi i nk/M), inverse exp(+2 pi i nk/M).
 // Contains barriers (see fft_multi).
-// PAD selects the padded slot map for contiguous transforms (ls = 1); a
-// padded transform occupies M + M/16 slots.  WAVE: every lane sharing the LDS
+// PAD selects the slot map (lds_slot); a padded transform occupies M + M/16
+// slots (rows of ls slots for PAD = 2).  WAVE: every lane sharing the LDS
 // regions is in the calling wave (see xsync); otherwise the whole block must
 // call.
-template <int M, bool INV, int NT, bool PAD, bool WAVE, typename L>
+template <int M, bool INV, int NT, int PAD, bool WAVE, typename L>
 __device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride, int ls,
                                           int j, const cd* __restrict__ tw) {
   using S = fft_shape<M>;
@@ -322,7 +325,7 @@ __device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride
   }
 }
 
-template <int M, bool INV, bool PAD, bool WAVE, typename L>
+template <int M, bool INV, int PAD, bool WAVE, typename L>
 __device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
                                     const cd* __restrict__ tw) {
   fft_multi<M, INV, 1, PAD, WAVE>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);

@@ -1,0 +1,164 @@
+// Adjoint column pass of the four-step SSFM (gfx950).
+//
+// The reverse sweep of the vector-Jacobian product runs on a work buffer that
+// holds, for each realisation, the forward state reconstructed backwards from
+// the span-end checkpoint and the cotangent dL/dA*.  Its row pass is k2_rows
+// with the conjugate dispersion operator; this file holds the column pass.
+#include "fft_dev.hpp"
+#include "kernel_common.hpp"
+#include "ssfm_internal.hpp"
+
+namespace ssfm {
+
+__device__ __forceinline__ double norm2(cd v) { return fma(v.re, v.re, v.im * v.im); }
+
+// ---------------------------------------------------------------------------
+// K3 adjoint: column tiles of the work buffer holding, for realisation b, the
+// reconstructed forward state (at b) and the cotangent dL/dA* (at batch + b).
+// Lanes: field f (0 state, 1 cotangent) x polarisation x C columns x T.
+//   AMODE_FIRST  state <- span-end checkpoint; both fields time -> mixed
+//   AMODE_NL     both mixed -> time; with y the state (output of the forward
+//                nonlinear step) and phi = kappa sum_q |y_q|^2:
+//                  state     x   = y e^{-i phi}            (inverse step)
+//                  cotangent g_x = g_y e^{-i phi} + 2 s kappa x,
+//                            s   = -Im sum_q conj(g_y,q) y_q (pullback)
+//                then both time -> mixed
+//   AMODE_LAST   cotangent mixed -> time, times the span gain (the pullback of
+//                the amplifier, applied at the end of the span's reverse sweep
+//                because everything in between is linear in the cotangent)
+// ---------------------------------------------------------------------------
+template <int N1, int C, int P, int AMODE>
+__global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
+  constexpr int T = N1 / 16;
+  extern __shared__ __align__(16) unsigned char lds_adj[];
+  cd* lds = reinterpret_cast<cd*>(lds_adj);
+  const int tid = threadIdx.x;
+  const int f = tid / (P * C * T);
+  const int rem0 = tid % (P * C * T);
+  const int p = rem0 / (C * T);
+  const int rem = rem0 % (C * T);
+  const int c = rem % C;
+  const int j = rem / C;
+  const int tiles = a.n2 / C;
+  const unsigned G = gridDim.x;
+  const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int64_t b = id / tiles;
+  const int n2 = (int)(id % tiles) * C + c;
+  float2* fp = a.work + ((f * a.batch + b) * P + p) * a.n + n2;
+  // FFT regions: one per (field, polarisation), N1 + N1/16 padded rows of C
+  constexpr int RS = (N1 + N1 / 16) * C;
+  cd* mylds = lds + (f * P + p) * RS + c;
+  const float2* src = fp;
+  if constexpr (AMODE == AMODE_FIRST) {
+    if (f == 0) src = a.ckpt + (b * P + p) * a.n + n2;
+  }
+  cd reg[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) reg[r] = load_c64(src + (int64_t)(j + T * r) * a.n2);
+
+  if constexpr (AMODE == AMODE_FIRST) {
+    fft<N1, false, 2, false>(reg, mylds, C, j, a.tw1);
+  } else if constexpr (AMODE == AMODE_NL) {
+    fft<N1, true, 2, false>(reg, mylds, C, j, a.tw1);
+    // exchange in natural (row, column) order: every lane publishes its
+    // value and reads only those it does not hold (state lanes: the other
+    // polarisation's state; cotangent lanes: both states and the other
+    // polarisation's cotangent)
+    __syncthreads();  // the inverse FFT's LDS reads are done
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds[((f * P + p) * N1 + j + T * r) * C + c] = reg[r];
+    __syncthreads();
+    constexpr int F = N1 * C;  // one field-polarisation plane
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = (j + T * r) * C + c;
+      if (f == 0) {
+        // x = y e^{-i phi}; the power is one add of per-polarisation terms
+        // (commutative, so every lane of the sample gets the same phase)
+        double pw = norm2(reg[r]);
+        if constexpr (P == 2) pw = pw + norm2(lds[(1 - p) * F + i]);
+        reg[r] = cmul(reg[r], unit_phasor(-a.kappa * pw));
+      } else {
+        // g_x = g_y e^{-i phi} + 2 s kappa x,  s = -Im sum_q conj(g_q) y_q
+        const cd yp = lds[p * F + i];
+        double pw = norm2(yp);
+        double s = fma(reg[r].im, yp.re, -reg[r].re * yp.im);
+        if constexpr (P == 2) {
+          const cd yo = lds[(1 - p) * F + i];
+          const cd go = lds[(P + 1 - p) * F + i];
+          pw = pw + norm2(yo);
+          s = fma(go.im, yo.re, fma(-go.re, yo.im, s));
+        }
+        const cd e = unit_phasor(-a.kappa * pw);  // e^{-i phi}
+        const cd x = cmul(yp, e);
+        const cd gx = cmul(reg[r], e);
+        const double w = 2.0 * s * a.kappa;
+        reg[r] = {fma(w, x.re, gx.re), fma(w, x.im, gx.im)};
+      }
+    }
+    fft<N1, false, 2, false>(reg, mylds, C, j, a.tw1);
+  }
+  if constexpr (AMODE == AMODE_LAST) {
+    // every lane transforms (the block barriers need all of them); only the
+    // cotangent is stored, the state is not needed past the span start
+    fft<N1, true, 2, false>(reg, mylds, C, j, a.tw1);
+    if (f == 0) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) reg[r] = round_c64(cscale(reg[r], a.gspan));
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+// padded FFT regions of both fields; the nonlinear exchange (2 P N1 C values)
+// fits in them
+template <int N1, int C, int P>
+constexpr size_t adj_lds_bytes() {
+  return (size_t)2 * P * (N1 + N1 / 16) * C * sizeof(cd);
+}
+
+template <int N1, int C, int P, int AMODE>
+static hipError_t launch_k3_adj(const AdjArgs& a, hipStream_t st) {
+  constexpr int T = N1 / 16;
+  const size_t lds = adj_lds_bytes<N1, C, P>();
+  const unsigned blocks = (unsigned)(a.batch * (a.n2 / C));
+  hipLaunchKernelGGL((k3_adj<N1, C, P, AMODE>), dim3(blocks), dim3(2 * P * C * T), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int N1, int C, int P, int AMODE>
+static hipError_t prepare_k3_adj() {
+  const size_t lds = adj_lds_bytes<N1, C, P>();
+  if (lds > 65536)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_adj<N1, C, P, AMODE>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
+// adjoint column tiles: 4 columns (2 at N1 = 512), both fields, FP64 LDS
+// (68 KB per workgroup with the padding)
+template <int N1, int P>
+static void fill_adj(KernelSet& ks) {
+  constexpr int C = N1 == 512 ? 2 : 4;
+  ks.adj[AMODE_FIRST] = &launch_k3_adj<N1, C, P, AMODE_FIRST>;
+  ks.adj[AMODE_NL] = &launch_k3_adj<N1, C, P, AMODE_NL>;
+  ks.adj[AMODE_LAST] = &launch_k3_adj<N1, C, P, AMODE_LAST>;
+  ks.adj_columns = C;
+  for (hipError_t e : {prepare_k3_adj<N1, C, P, AMODE_FIRST>(), prepare_k3_adj<N1, C, P, AMODE_NL>(),
+                       prepare_k3_adj<N1, C, P, AMODE_LAST>()})
+    if (e != hipSuccess) ks.prepare = e;
+}
+
+void select_adjoint_kernels(int n1, int n_pol, KernelSet& ks) {
+  switch (n1) {
+    case 128: if (n_pol == 1) fill_adj<128, 1>(ks); else fill_adj<128, 2>(ks); break;
+    case 256: if (n_pol == 1) fill_adj<256, 1>(ks); else fill_adj<256, 2>(ks); break;
+    case 512: if (n_pol == 1) fill_adj<512, 1>(ks); else fill_adj<512, 2>(ks); break;
+    default: break;
+  }
+}
+
+}  // namespace ssfm

@@ -103,4 +103,8 @@ struct KernelSet {
 // false if no instantiation exists for that size.
 bool select_kernels(int64_t n, int n_pol, KernelSet& ks);
 
+// Fill ks.adj for the four-step column length n1 (leaves it empty if there is
+// no adjoint instantiation for that length).
+void select_adjoint_kernels(int n1, int n_pol, KernelSet& ks);
+
 }  // namespace ssfm

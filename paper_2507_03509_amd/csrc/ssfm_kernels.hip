@@ -17,6 +17,8 @@
 //   k2_rows  four-step row pass: row FFT -> dispersion multiply -> row IFFT.
 //   k3_cols  four-step column pass: twiddle* -> column IFFT -> nonlinear
 //            phase or amplifier + ASE -> column FFT -> twiddle.
+// The adjoint's column pass (k3_adj) is in its own translation unit; its row
+// pass is k2_rows with the conjugate dispersion operator.
 //
 // Four-step indexing (N = N1 * N2, time index n = n1 N2 + n2, frequency index
 // k = k1 + N1 k2): the column FFT over n1 gives k1, the twiddle W_N^{n2 k1}
@@ -25,59 +27,11 @@
 // the same order.  Between passes the field sits in HBM in the mixed
 // (k1, n2) domain, so a split step costs exactly two read+write sweeps.
 #include "fft_dev.hpp"
+#include "kernel_common.hpp"
 #include "philox_dev.hpp"
 #include "ssfm_internal.hpp"
 
 namespace ssfm {
-
-__device__ __forceinline__ cd load_c64(const float2* p) {
-  float2 v = *p;
-  return {(double)v.x, (double)v.y};
-}
-__device__ __forceinline__ void store_c64(float2* p, cd v) {
-  *p = make_float2((float)v.re, (float)v.im);
-}
-// The state at a span boundary is the complex64 field: rounding to it there
-// makes a run split at span boundaries identical, bit for bit, to one call.
-__device__ __forceinline__ cd round_c64(cd v) {
-  return {(double)(float)v.re, (double)(float)v.im};
-}
-
-// exp(i phi) in FP64.  For |phi| <= 1/4 (the nonlinear phase of one split
-// step is ~1e-2 rad on the workloads here) the Taylor series of sin to phi^11
-// and cos to phi^10, truncation below 1e-15 relative, so the rotation is
-// unit-modulus to FP64 rounding.  Larger angles: single-precision sine and
-// cosine, then one Newton step on the modulus in FP64 (a rotation whose
-// modulus carries a single-precision rounding would bias the power at every
-// step).
-__device__ __forceinline__ cd unit_phasor(double phi) {
-  if (fabs(phi) <= 0.25) {
-    const double x2 = phi * phi;
-    double ps = fma(x2, -1.0 / 39916800.0, 1.0 / 362880.0);
-    ps = fma(ps, x2, -1.0 / 5040.0);
-    ps = fma(ps, x2, 1.0 / 120.0);
-    ps = fma(ps, x2, -1.0 / 6.0);
-    double pc = fma(x2, -1.0 / 3628800.0, 1.0 / 40320.0);
-    pc = fma(pc, x2, -1.0 / 720.0);
-    pc = fma(pc, x2, 1.0 / 24.0);
-    pc = fma(pc, x2, -0.5);
-    return {fma(pc, x2, 1.0), fma(ps * x2, phi, phi)};
-  }
-  float s, c;
-  sincosf((float)phi, &s, &c);
-  const double cr = c, sr = s;
-  const double m = fma(cr, cr, sr * sr);
-  const double f = fma(-0.5, m, 1.5);
-  return {cr * f, sr * f};
-}
-
-// twiddle W_N^m from the two-level table (m < N): twA[a] = W_N^{a N2},
-// twB[b] = W_N^b
-__device__ __forceinline__ cd four_step_twiddle(const cd* __restrict__ twA,
-                                                const cd* __restrict__ twB, int m, int log2_n2,
-                                                int n2) {
-  return cmul(twA[m >> log2_n2], twB[m & (n2 - 1)]);
-}
 
 // ---------------------------------------------------------------------------
 // K2: rows of length N2 (contiguous), WG lanes, FP32 LDS exchange.
@@ -224,97 +178,6 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
   if constexpr (MODE != MODE_LAST) {
     // time -> mixed domain: column FFT
     fft<N1, false, false, false>(reg, mylds, C, j, a.tw1);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
-}
-
-// ---------------------------------------------------------------------------
-// K3 adjoint: column tiles of the work buffer holding, for realisation b, the
-// reconstructed forward state (at b) and the cotangent dL/dA* (at batch + b).
-// Lanes: field f (0 state, 1 cotangent) x polarisation x C columns x T.
-//   AMODE_FIRST  state <- span-end checkpoint; both fields time -> mixed
-//   AMODE_NL     both mixed -> time; with y the state (output of the forward
-//                nonlinear step) and phi = kappa sum_q |y_q|^2:
-//                  state     x   = y e^{-i phi}            (inverse step)
-//                  cotangent g_x = g_y e^{-i phi} + 2 s kappa x,
-//                            s   = -Im sum_q conj(g_y,q) y_q (pullback)
-//                then both time -> mixed
-//   AMODE_LAST   cotangent mixed -> time, times the span gain (the pullback of
-//                the amplifier, applied at the end of the span's reverse sweep
-//                because everything in between is linear in the cotangent)
-// ---------------------------------------------------------------------------
-template <int N1, int C, int P, int AMODE>
-__global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
-  constexpr int T = N1 / 16;
-  extern __shared__ __align__(16) unsigned char lds_adj[];
-  cd* lds = reinterpret_cast<cd*>(lds_adj);
-  const int tid = threadIdx.x;
-  const int f = tid / (P * C * T);
-  const int rem0 = tid % (P * C * T);
-  const int p = rem0 / (C * T);
-  const int rem = rem0 % (C * T);
-  const int c = rem % C;
-  const int j = rem / C;
-  const int tiles = a.n2 / C;
-  const unsigned G = gridDim.x;
-  const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
-  const int64_t b = id / tiles;
-  const int n2 = (int)(id % tiles) * C + c;
-  float2* fp = a.work + ((f * a.batch + b) * P + p) * a.n + n2;
-  cd* mylds = lds + (f * P + p) * (N1 * C) + c;
-  const float2* src = fp;
-  if constexpr (AMODE == AMODE_FIRST) {
-    if (f == 0) src = a.ckpt + (b * P + p) * a.n + n2;
-  }
-  cd reg[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) reg[r] = load_c64(src + (int64_t)(j + T * r) * a.n2);
-
-  if constexpr (AMODE == AMODE_FIRST) {
-    fft<N1, false, false, false>(reg, mylds, C, j, a.tw1);
-  } else if constexpr (AMODE == AMODE_NL) {
-    fft<N1, true, false, false>(reg, mylds, C, j, a.tw1);
-    __syncthreads();  // the inverse FFT's LDS reads are done
-#pragma unroll
-    for (int r = 0; r < 16; ++r) lds[((f * P + p) * N1 + j + T * r) * C + c] = reg[r];
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = (j + T * r) * C + c;
-      double pw = 0.0;
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const cd yq = lds[q * N1 * C + i];
-        pw = fma(yq.re, yq.re, fma(yq.im, yq.im, pw));
-      }
-      const cd e = unit_phasor(-a.kappa * pw);  // e^{-i phi}
-      const cd yp = lds[p * N1 * C + i];
-      const cd x = cmul(yp, e);
-      if (f == 0) {
-        reg[r] = x;
-      } else {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-          const cd yq = lds[q * N1 * C + i];
-          const cd gq = lds[(P + q) * N1 * C + i];
-          s -= fma(gq.re, yq.im, -gq.im * yq.re);  // -Im(conj(g) y)
-        }
-        const cd gx = cmul(reg[r], e);
-        const double w = 2.0 * s * a.kappa;
-        reg[r] = {fma(w, x.re, gx.re), fma(w, x.im, gx.im)};
-      }
-    }
-    fft<N1, false, false, false>(reg, mylds, C, j, a.tw1);
-  }
-  if constexpr (AMODE == AMODE_LAST) {
-    // every lane transforms (the block barriers need all of them); only the
-    // cotangent is stored, the state is not needed past the span start
-    fft<N1, true, false, false>(reg, mylds, C, j, a.tw1);
-    if (f == 0) return;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) reg[r] = round_c64(cscale(reg[r], a.gspan));
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
@@ -476,38 +339,6 @@ static hipError_t prepare_k3_one() {
   return hipSuccess;
 }
 
-template <int N1, int C, int P, int AMODE>
-static hipError_t launch_k3_adj(const AdjArgs& a, hipStream_t st) {
-  constexpr int T = N1 / 16;
-  const size_t lds = (size_t)2 * P * C * N1 * sizeof(cd);
-  const unsigned blocks = (unsigned)(a.batch * (a.n2 / C));
-  hipLaunchKernelGGL((k3_adj<N1, C, P, AMODE>), dim3(blocks), dim3(2 * P * C * T), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int N1, int C, int P, int AMODE>
-static hipError_t prepare_k3_adj() {
-  const size_t lds = (size_t)2 * P * C * N1 * sizeof(cd);
-  if (lds > 65536)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_adj<N1, C, P, AMODE>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return hipSuccess;
-}
-
-// adjoint column tiles: 4 columns (2 at N1 = 512), both fields, FP64 LDS
-// (64 KB per workgroup)
-template <int N1, int P>
-static void fill_adj(KernelSet& ks) {
-  constexpr int C = N1 == 512 ? 2 : 4;
-  ks.adj[AMODE_FIRST] = &launch_k3_adj<N1, C, P, AMODE_FIRST>;
-  ks.adj[AMODE_NL] = &launch_k3_adj<N1, C, P, AMODE_NL>;
-  ks.adj[AMODE_LAST] = &launch_k3_adj<N1, C, P, AMODE_LAST>;
-  ks.adj_columns = C;
-  for (hipError_t e : {prepare_k3_adj<N1, C, P, AMODE_FIRST>(), prepare_k3_adj<N1, C, P, AMODE_NL>(),
-                       prepare_k3_adj<N1, C, P, AMODE_LAST>()})
-    if (e != hipSuccess) ks.prepare = e;
-}
-
 // ---- dispatch tables ------------------------------------------------------
 
 static int log2i(int64_t v) {
@@ -576,21 +407,22 @@ bool select_kernels(int64_t n, int n_pol, KernelSet& ks) {
   if (pr != hipSuccess) ks.prepare = pr;
   switch (ks.n1) {
     case 128:
-      if (n_pol == 1) { fill_cols<128, 1>(ks); fill_adj<128, 1>(ks); }
-      else { fill_cols<128, 2>(ks); fill_adj<128, 2>(ks); }
+      if (n_pol == 1) { fill_cols<128, 1>(ks); }
+      else { fill_cols<128, 2>(ks); }
       break;
     case 256:
-      if (n_pol == 1) { fill_cols<256, 1>(ks); fill_adj<256, 1>(ks); }
-      else { fill_cols<256, 2>(ks); fill_adj<256, 2>(ks); }
+      if (n_pol == 1) { fill_cols<256, 1>(ks); }
+      else { fill_cols<256, 2>(ks); }
       break;
     case 512:
-      if (n_pol == 1) { fill_cols<512, 1>(ks); fill_adj<512, 1>(ks); }
-      else { fill_cols<512, 2>(ks); fill_adj<512, 2>(ks); }
+      if (n_pol == 1) { fill_cols<512, 1>(ks); }
+      else { fill_cols<512, 2>(ks); }
       break;
     default: return false;
   }
   for (const FourStepKernels* k : {&ks.wide, &ks.mid, &ks.narrow})
     if (k->prepare_status != hipSuccess) ks.prepare = k->prepare_status;
+  select_adjoint_kernels(ks.n1, n_pol, ks);
   return true;
 }
 
