@@ -15,3 +15,9 @@ __all__ = ["si_params", "angular_frequency", "linear_factor",
            "nl_step_length", "linear_step", "nl_step", "ase_words",
            "uniform_from_words", "ase_noise", "edfa", "propagate",
            "propagate_batch", "nl_pullback", "adjoint"]
+
+from .ldbp_ref import (fir, nl_rotate, ldbp_forward, matched_filter_samples,
+                       mse_loss, mse_grad, ldbp_backward, init_params)
+
+__all__ += ["fir", "nl_rotate", "ldbp_forward", "matched_filter_samples",
+            "mse_loss", "mse_grad", "ldbp_backward", "init_params"]

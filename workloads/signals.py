@@ -13,8 +13,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["dbm_to_watt", "qam16_symbols", "rrc_response", "shaped_field",
-           "dual_pol_field", "wdm_field", "make_field"]
+__all__ = ["dbm_to_watt", "qam16_symbols", "rrc_response", "rrc_taps",
+           "shaped_field", "dual_pol_field", "wdm_field", "make_field"]
 
 
 def dbm_to_watt(p_dbm: float) -> float:
@@ -41,6 +41,28 @@ def rrc_response(f: np.ndarray, symbol_rate: float, rolloff: float) -> np.ndarra
         out[band] = np.sqrt(0.5 * (1.0 + np.cos(
             math.pi / (rolloff * symbol_rate) * (a[band] - f1))))
     return out
+
+
+def rrc_taps(sps: int, rolloff: float, half: int) -> np.ndarray:
+    """Real root-raised-cosine matched filter of 2 half + 1 taps at ``sps``
+    samples per symbol, t = j / sps symbols, unit energy (closed form of the
+    RRC impulse response; the removable singularities at t = 0 and
+    |t| = 1 / (4 rolloff) take their limits)."""
+    b = rolloff
+    out = np.empty(2 * half + 1)
+    for i, j in enumerate(range(-half, half + 1)):
+        t = j / sps
+        if j == 0:
+            v = 1.0 + b * (4.0 / math.pi - 1.0)
+        elif b > 0 and abs(abs(4.0 * b * t) - 1.0) < 1e-12:
+            v = (b / math.sqrt(2.0)) * ((1 + 2 / math.pi) * math.sin(math.pi / (4 * b))
+                                        + (1 - 2 / math.pi) * math.cos(math.pi / (4 * b)))
+        else:
+            num = math.sin(math.pi * t * (1 - b)) + 4 * b * t * math.cos(math.pi * t * (1 + b))
+            den = math.pi * t * (1 - (4 * b * t) ** 2)
+            v = num / den
+        out[i] = v
+    return out / math.sqrt(np.sum(out ** 2))
 
 
 def shaped_field(symbols: np.ndarray, sps: int, symbol_rate: float,
