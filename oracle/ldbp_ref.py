@@ -41,9 +41,15 @@ or reordered.
 The initial parameters ``init_params`` come from the link: step k
 back-propagates 1/S of a span (S steps per span, from the last span to the
 first) with the truncated impulse response of the inverse dispersion as
-taps (the least-squares T-tap fit of that response over the full band) and
-the midpoint-weighted nonlinear coefficient of the forward model with the
-opposite sign.
+taps (the least-squares T-tap fit of that response over the full band),
+scaled by the peak gain of the truncated filter, and the midpoint-weighted
+nonlinear coefficient of the forward model with the opposite sign.  The
+scaling is a reading of ours: a truncated all-pass response ripples above
+unit gain at some frequencies (1.33 for 15 taps over 40 km at 128 GS/s), and
+K cascaded steps would amplify those by the K-th power (285 for K = 20),
+noise and rounding included; scaled, every step is contractive.  When T
+covers the whole circular response the filter is all-pass and the scale is
+one.
 """
 
 from __future__ import annotations
@@ -166,6 +172,11 @@ def init_params(link, n_taps: int, steps_per_span: int):
     ir = np.fft.ifft(resp)
     c = (n_taps - 1) // 2
     base = np.array([ir[(t - c) % n] for t in range(n_taps)])
+    # peak gain of the truncated filter on the n-point grid
+    kernel = np.zeros(n, dtype=np.complex128)
+    for t in range(n_taps):
+        kernel[(t - c) % n] += base[t]
+    base = base / np.max(np.abs(np.fft.fft(kernel)))
     gspan = math.sqrt(p["gain"]) * math.exp(-p["alpha"] * p["span_m"] / 2.0)
     k_total = p["n_spans"] * steps_per_span
     taps = np.empty((k_total, n_taps), dtype=np.complex128)

@@ -1,0 +1,601 @@
+// Learned digital back-propagation kernels (gfx950).
+//
+// The model alternates a short complex FIR filter (circular, both
+// polarisations) with a Kerr phase rotation.  A workgroup owns a tile of w
+// samples of one realisation plus a halo on each side: one step needs 7
+// neighbours per side, so a launch fusing q steps carries a halo of 7 q and
+// never exchanges data with other workgroups.  The tile's state lives in LDS
+// in FP64; each lane owns R = 4 consecutive samples and reads the 18-sample
+// window of its 4 outputs from LDS into registers (4.5 LDS reads per output
+// instead of 15).  HBM sees the state once per launch.
+//
+// LDS slot of sample i: j + floor(j / 4), j = i + 8 -- one pad slot per 4
+// samples.  For the lane owning samples 4 l .. 4 l + 3 the slot of window
+// sample d is 5 l + (a constant of d), so a window is one base address plus
+// immediate offsets, and the 8 lanes of one 128-byte LDS access fall on 8
+// different 16-byte bank groups for every d.
+//
+// Backward: one launch per span (steps [k0, k0 + S)).  The span's inner
+// states are recomputed from its start checkpoint with the forward code
+// (bitwise the forward's values: the forward rounds to complex64 only at
+// span boundaries), then each step is pulled back in reverse: the Kerr step
+// pointwise from its output z (y = z e^{-i phi}, |y| = |z|), the FIR step as
+// the correlation with conj(h) through an LDS window.  Tap and xi gradients
+// are accumulated per lane over its interior samples, reduced across the
+// wave by recursive halving (32 values in 32 shuffle-adds) and across the
+// workgroup in LDS, and written as per-workgroup partials that a last kernel
+// sums in a fixed order.
+#include "kernel_common.hpp"
+#include "ldbp_internal.hpp"
+
+namespace ssfm {
+namespace ldbp {
+
+// Sample i of a region lives at slot lslot(i) of its LDS array, for
+// -GUARD <= i < region + GUARD; the guard slots hold zeros, so the windows
+// of the edge lanes need no bounds check.
+__device__ __forceinline__ int lslot(int i) {
+  const int j = i + GUARD;
+  return j + (j >> 2);
+}
+
+__device__ __forceinline__ double norm2(cd v) { return fma(v.re, v.re, v.im * v.im); }
+
+// acc + a b
+__device__ __forceinline__ cd cmac(cd acc, cd a, cd b) {
+  return {fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im))};
+}
+
+// exp(i phi) to FP64 accuracy for |phi| < 2^20: Cody-Waite reduction
+// r = phi - q pi/2 with pi/2 split in two parts (the product q * PIO2_HI is
+// exact for |q| < 2^20), Taylor series of sin (to r^15) and cos (to r^16) on
+// |r| <= pi/4, whose next terms are below 5e-17, and the quadrant rotation
+// by i^q.  Register-light, with no data-dependent branch.
+__device__ __forceinline__ cd phasor64(double phi) {
+  constexpr double TWO_OVER_PI = 0.63661977236758134308;
+  constexpr double PIO2_HI = 1.5707963267341256141;   // 33 significant bits
+  constexpr double PIO2_LO = 6.0771005065061922e-11;  // pi/2 - PIO2_HI
+  const double q = rint(phi * TWO_OVER_PI);
+  const double r = fma(-q, PIO2_LO, fma(-q, PIO2_HI, phi));
+  const double r2 = r * r;
+  double ps = fma(r2, -1.0 / 1307674368000.0, 1.0 / 6227020800.0);
+  ps = fma(ps, r2, -1.0 / 39916800.0);
+  ps = fma(ps, r2, 1.0 / 362880.0);
+  ps = fma(ps, r2, -1.0 / 5040.0);
+  ps = fma(ps, r2, 1.0 / 120.0);
+  ps = fma(ps, r2, -1.0 / 6.0);
+  const double sn = fma(ps * r2, r, r);
+  double pc = fma(r2, 1.0 / 20922789888000.0, -1.0 / 87178291200.0);
+  pc = fma(pc, r2, 1.0 / 479001600.0);
+  pc = fma(pc, r2, -1.0 / 3628800.0);
+  pc = fma(pc, r2, 1.0 / 40320.0);
+  pc = fma(pc, r2, -1.0 / 720.0);
+  pc = fma(pc, r2, 1.0 / 24.0);
+  pc = fma(pc, r2, -0.5);
+  const double cs = fma(pc, r2, 1.0);
+  const int quad = (int)(((long long)q) & 3);
+  // e^{i(r + quad pi/2)} = i^quad e^{ir}
+  return quad == 0 ? cd{cs, sn} : quad == 1 ? cd{-sn, cs} : quad == 2 ? cd{-cs, -sn} : cd{sn, -cs};
+}
+
+// Step k's filter from the padded [K][15] copy (uniform loads: the taps
+// sit in scalar registers).
+__device__ __forceinline__ void load_taps(const cd* __restrict__ taps15, int k, cd (&h)[TAPS]) {
+#pragma unroll
+  for (int t = 0; t < TAPS; ++t) h[t] = taps15[k * TAPS + t];
+}
+
+// Window sample d of the lane: a[base - HC + d].
+__device__ __forceinline__ cd window_at(const cd* a, int base, int d) {
+  return a[lslot(base - HC + d)];
+}
+
+// y[r] = sum_t h[t] a[base + r + HC - t]: the FIR step at the lane's samples.
+// The window is streamed: each of its R + 14 samples updates the outputs that
+// use it and is dropped, so only the outputs stay live.
+__device__ __forceinline__ void fir_own(const cd* a, int base, const cd (&h)[TAPS], cd (&y)[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) y[r] = cd{0.0, 0.0};
+#pragma unroll
+  for (int d = 0; d < R + 2 * HC; ++d) {
+    const cd v = window_at(a, base, d);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int t = r + 2 * HC - d;
+      if (t >= 0 && t < TAPS) y[r] = cmac(y[r], h[t], v);
+    }
+  }
+}
+
+// Kerr step in place: y_p <- y_p exp(i xi sum_q |y_q|^2).  The power is one
+// add of per-polarisation terms (commutative: every lane forms the same sum).
+template <int P>
+__device__ __forceinline__ void kerr(cd (&y)[P][R], double xi) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double pw = norm2(y[0][r]);
+    if constexpr (P == 2) pw = pw + norm2(y[1][r]);
+    const cd e = phasor64(xi * pw);
+#pragma unroll
+    for (int p = 0; p < P; ++p) y[p][r] = cmul(y[p][r], e);
+  }
+}
+
+// One forward step at the lane's samples, reading state array st.
+template <int P>
+__device__ __forceinline__ void step_own(const cd* st, int ls, int base,
+                                         const cd* __restrict__ taps15, const double* __restrict__ xi,
+                                         int k, cd (&y)[P][R]) {
+  cd h[TAPS];
+  load_taps(taps15, k, h);
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    fir_own(st + p * ls, base, h, y[p]);
+    // keep the next polarisation's window loads behind this one's FMAs: the
+    // two windows together would not fit the register budget
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  kerr<P>(y, xi[k]);
+}
+
+// Zero the guard slots of `arrays` consecutive LDS arrays of stride ls
+// holding a region of `region` samples.
+__device__ __forceinline__ void zero_guards(cd* a, int arrays, int ls, int region) {
+  for (int q = threadIdx.x; q < arrays * 2 * GUARD; q += blockDim.x) {
+    const int arr = q / (2 * GUARD), e = q % (2 * GUARD);
+    const int i = e < GUARD ? e - GUARD : region + (e - GUARD);
+    a[arr * ls + lslot(i)] = cd{0.0, 0.0};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(512) void ldbp_fwd(FwdArgs a, const cd* __restrict__ taps15,
+                                                 const double* __restrict__ xi) {
+  extern __shared__ __align__(16) unsigned char smem_f[];
+  cd* st = reinterpret_cast<cd*>(smem_f);
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x / a.tiles;
+  const int tile = (int)(blockIdx.x % a.tiles);
+  const int64_t n0 = (int64_t)tile * a.w - a.halo;
+  const int64_t nm = a.n - 1;
+  const float2* src = a.src + b * P * a.n;
+  zero_guards(st, P, a.ls, a.region);
+  for (int i = tid; i < a.region; i += blockDim.x) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) st[p * a.ls + lslot(i)] = load_c64(src + p * a.n + ((n0 + i) & nm));
+  }
+  __syncthreads();
+  const int base = tid * R;
+  const bool active = base < a.region;
+  for (int k = a.k0; k < a.k1; ++k) {
+    cd y[P][R];
+    const bool span_end = (k + 1) % a.spans_steps == 0;
+    if (active) {
+      step_own<P>(st, a.ls, base, taps15, xi, k, y);
+      if (span_end) {
+        // the state at a span boundary is the complex64 field
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int r = 0; r < R; ++r) y[p][r] = round_c64(y[p][r]);
+      }
+    }
+    __syncthreads();  // every window of this step is read
+    if (active) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int r = 0; r < R; ++r) st[p * a.ls + lslot(base + r)] = y[p][r];
+    }
+    __syncthreads();
+    if (a.ckpt && span_end && k + 1 < a.k1) {
+      float2* cp = a.ckpt + ((int64_t)((k + 1) / a.spans_steps - 1) * a.batch + b) * P * a.n +
+                   (int64_t)tile * a.w;
+      for (int i = tid; i < a.w; i += blockDim.x) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) store_c64(cp + p * a.n + i, st[p * a.ls + lslot(a.halo + i)]);
+      }
+    }
+  }
+  float2* dst = a.dst + b * P * a.n + (int64_t)tile * a.w;
+  for (int i = tid; i < a.w; i += blockDim.x) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) store_c64(dst + p * a.n + i, st[p * a.ls + lslot(a.halo + i)]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+
+// Sum v[0..31] over the 64 lanes of the wave by recursive halving: in round
+// r lanes exchange with lane ^ (1 << r) the half of their values they do not
+// keep, so each round halves the values per lane.  Returns, on lane l, the
+// wave sum of value index bitrev5(l & 31) (lanes l and l + 32 agree).
+__device__ __forceinline__ double wave_sum32(double (&v)[NRED]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const int half = NRED >> (r + 1);
+    const bool upper = (lane >> r) & 1;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const double lo = v[i], hi = v[i + half];
+      const double send = upper ? lo : hi;
+      const double keep = upper ? hi : lo;
+      v[i] = keep + __shfl_xor(send, 1 << r, 64);
+    }
+  }
+  return v[0] + __shfl_xor(v[0], 32, 64);
+}
+
+__device__ __forceinline__ int bitrev5(int l) {
+  return ((l & 1) << 4) | ((l & 2) << 2) | (l & 4) | ((l & 8) >> 2) | ((l & 16) >> 4);
+}
+
+// Sum v over the workgroup into out[0..31] (written by threads 0..31).
+// red: nwaves * 32 doubles of LDS.  Contains barriers.
+__device__ __forceinline__ void block_sum32(double (&v)[NRED], double* red, double* out) {
+  const double s = wave_sum32(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane < 32) red[wave * NRED + bitrev5(lane)] = s;
+  __syncthreads();
+  if (threadIdx.x < NRED) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w * NRED + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Backward of one span
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict__ taps15,
+                                                 const double* __restrict__ xis) {
+  extern __shared__ __align__(16) unsigned char smem_b[];
+  // [X_0 .. X_{S-1}][G] states and gradient, P * ls each, then the reduction
+  cd* xs_lds = reinterpret_cast<cd*>(smem_b);
+  const int plane = P * a.ls;
+  cd* G = xs_lds + a.s_steps * plane;
+  double* red = reinterpret_cast<double*>(G + plane);
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x / a.tiles;
+  const int tile = (int)(blockIdx.x % a.tiles);
+  const int64_t n0 = (int64_t)tile * a.w - a.halo;
+  const int64_t nm = a.n - 1;
+  const int64_t row0 = b * P * a.n;
+  zero_guards(xs_lds, P * (a.s_steps + 1), a.ls, a.region);
+  for (int i = tid; i < a.region; i += blockDim.x) {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      xs_lds[p * a.ls + lslot(i)] = load_c64(a.x0 + row0 + p * a.n + ((n0 + i) & nm));
+  }
+  const int base = tid * R;
+  const bool active = base < a.region;
+  __syncthreads();
+  // inner states X_1 .. X_{S-1} (no rounding inside a span, as in the forward)
+  for (int j = 1; j < a.s_steps; ++j) {
+    cd y[P][R];
+    if (active) {
+      step_own<P>(xs_lds + (j - 1) * plane, a.ls, base, taps15, xis, a.k0 + j - 1, y);
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int r = 0; r < R; ++r) xs_lds[j * plane + p * a.ls + lslot(base + r)] = y[p][r];
+    }
+    __syncthreads();
+  }
+  // the lane's samples of the span-end state and of its gradient (loaded
+  // after the recompute, which needs the registers)
+  cd z[P][R], g[P][R];
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t idx = row0 + p * a.n + ((n0 + base + r) & nm);
+        z[p][r] = load_c64(a.xs + idx);
+        g[p][r] = load_c64(a.g_in + idx);
+      }
+  }
+  for (int j = a.s_steps - 1; j >= 0; --j) {
+    const int k = a.k0 + j;
+    const double xi = xis[k];
+    const cd* X = xs_lds + j * plane;
+    if (j < a.s_steps - 1 && active) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[p][r] = xs_lds[(j + 1) * plane + p * a.ls + lslot(base + r)];
+    }
+    // Kerr pullback at the lane's samples (z = output, g = its gradient)
+    double xi_part = 0.0;
+    cd gy[P][R];
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double pw = norm2(z[0][r]);
+        if constexpr (P == 2) pw = pw + norm2(z[1][r]);
+        const cd e = phasor64(-xi * pw);  // e^{-i phi}
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) s = fma(g[p][r].im, z[p][r].re, fma(-g[p][r].re, z[p][r].im, s));
+        const double w2 = 2.0 * xi * s;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const cd y = cmul(z[p][r], e);
+          const cd ge = cmul(g[p][r], e);
+          gy[p][r] = {fma(w2, y.re, ge.re), fma(w2, y.im, ge.im)};
+        }
+        const int i = base + r;
+        if (i >= a.halo && i < a.halo + a.w) xi_part = fma(pw, s, xi_part);
+      }
+    }
+    __syncthreads();  // earlier readers of G are done
+    if (active) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int r = 0; r < R; ++r) G[p * a.ls + lslot(base + r)] = gy[p][r];
+    }
+    __syncthreads();
+    double acc[NRED];
+#pragma unroll
+    for (int v = 0; v < NRED; ++v) acc[v] = 0.0;
+    // FIR pullback gx[m] = sum_t conj(h[t]) gy[m - c + t], then the tap
+    // gradient dL/dh[t] += gy[m - c + t] conj(x[m]) over the interior samples
+    // m, in two passes over the window so that the 32 accumulators are not
+    // live together with the pullback's outputs and window
+    if (active) {
+      cd h[TAPS];
+      load_taps(taps15, k, h);
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) g[p][r] = cd{0.0, 0.0};
+        // window sample d = gy[base - c + d] meets output r through t = d - r
+#pragma unroll
+        for (int d = 0; d < R + 2 * HC; ++d) {
+          const cd v = window_at(G + p * a.ls, base, d);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int t = d - r;
+            if (t >= 0 && t < TAPS) g[p][r] = cmac(g[p][r], cd{h[t].re, -h[t].im}, v);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one polarisation's window at a time
+      }
+      if (base + R > a.halo && base < a.halo + a.w) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          cd xm[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int i = base + r;
+            xm[r] = (i >= a.halo && i < a.halo + a.w) ? X[p * a.ls + lslot(i)] : cd{0.0, 0.0};
+          }
+#pragma unroll
+          for (int d = 0; d < R + 2 * HC; ++d) {
+            const cd v = window_at(G + p * a.ls, base, d);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const int t = d - r;
+              if (t >= 0 && t < TAPS) {
+                const cd q = cmulc(v, xm[r]);
+                acc[2 * t] += q.re;
+                acc[2 * t + 1] += q.im;
+              }
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    acc[2 * TAPS] = xi_part;
+    block_sum32(acc, red, a.partial + ((int64_t)k * gridDim.x + blockIdx.x) * NRED);
+  }
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = base + r;
+        if (i >= a.halo && i < a.halo + a.w) store_c64(a.g_out + row0 + p * a.n + (n0 + i), g[p][r]);
+      }
+  }
+}
+
+// taps15[k][t] = the caller's taps[k][t - off] (zero outside), off = 7 - (T-1)/2
+__global__ __launch_bounds__(256) void ldbp_pad_taps(const cd* __restrict__ taps, int n_steps,
+                                                     int n_taps, cd* taps15) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_steps * TAPS) return;
+  const int k = q / TAPS, t = q % TAPS, s = t - (HC - (n_taps - 1) / 2);
+  taps15[q] = (s >= 0 && s < n_taps) ? taps[(int64_t)k * n_taps + s] : cd{0.0, 0.0};
+}
+
+// Parameter gradients: sum the per-workgroup partials of every step in a
+// fixed order.  One workgroup of 256 lanes per step.
+__global__ __launch_bounds__(256) void ldbp_reduce(const double* __restrict__ partial, int blocks,
+                                                   int n_taps, cd* grad_taps, double* grad_xi) {
+  __shared__ double red[8][NRED];
+  const int k = blockIdx.x;
+  const int v = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  double s = 0.0;
+  for (int i = grp; i < blocks; i += 8) s += partial[((int64_t)k * blocks + i) * NRED + v];
+  red[grp][v] = s;
+  __syncthreads();
+  if (threadIdx.x < NRED) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += red[q][v];
+    red[0][v] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < n_taps) {
+    const int tt = threadIdx.x + HC - (n_taps - 1) / 2;
+    grad_taps[(int64_t)k * n_taps + threadIdx.x] = cd{red[0][2 * tt], red[0][2 * tt + 1]};
+  }
+  if (threadIdx.x == 0) grad_xi[k] = red[0][2 * TAPS];
+}
+
+// ---------------------------------------------------------------------------
+// Loss: matched filter at the symbol instants
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ldbp_loss(LossArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_l[];
+  float2* zs = reinterpret_cast<float2*>(smem_l);
+  __shared__ double red[4];
+  const int64_t row = blockIdx.x / a.tiles;
+  const int tile = (int)(blockIdx.x % a.tiles);
+  const int64_t m0 = (int64_t)tile * a.ms;
+  // samples sps m0 - R .. sps (m0 + ms - 1) + R
+  const int span = a.sps * (a.ms - 1) + 2 * a.mf_half + 1;
+  const int64_t s0 = a.sps * m0 - a.mf_half;
+  const int64_t nm = a.n - 1;
+  const float2* zr = a.z + row * a.n;
+  for (int i = threadIdx.x; i < span; i += blockDim.x) zs[i] = zr[(s0 + i) & nm];
+  __syncthreads();
+  double part = 0.0;
+  if (threadIdx.x < a.ms) {
+    const int c = a.sps * threadIdx.x + a.mf_half;  // local index of sample sps m
+    cd u{0.0, 0.0};
+    for (int j = -a.mf_half; j <= a.mf_half; ++j) {
+      const float2 v = zs[c - j];
+      const double gj = a.mf[j + a.mf_half];
+      u.re = fma(gj, (double)v.x, u.re);
+      u.im = fma(gj, (double)v.y, u.im);
+    }
+    const int64_t m = m0 + threadIdx.x;
+    const float2 sv = a.sym[row * a.m + m];
+    const cd e{u.re - (double)sv.x, u.im - (double)sv.y};
+    part = norm2(e);
+    a.ubar[row * a.m + m] = cscale(e, a.scale);
+  }
+  // workgroup sum in a fixed order
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) t += red[w];
+    a.partial[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void ldbp_loss_total(const double* __restrict__ partial, int count,
+                                                       double inv_count, double* loss) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) s += partial[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *loss = (red[0] + red[1] + red[2] + red[3]) * inv_count;
+}
+
+// grad[n] = sum_m mf[sps m - n + R] ubar[m] over the symbols within R of n
+__global__ __launch_bounds__(256) void ldbp_mf_adjoint(MfAdjArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_m[];
+  cd* us = reinterpret_cast<cd*>(smem_m);
+  const int64_t row = blockIdx.x / a.tiles;
+  const int tile = (int)(blockIdx.x % a.tiles);
+  const int64_t nb = (int64_t)tile * a.ns;
+  // symbols m in [floor((nb - R) / sps), floor((nb + ns - 1 + R) / sps)]
+  const int64_t mlo = (nb - a.mf_half >= 0) ? (nb - a.mf_half) / a.sps
+                                            : -((a.mf_half - nb + a.sps - 1) / a.sps);
+  const int64_t mhi = (nb + a.ns - 1 + a.mf_half) / a.sps;
+  const int cnt = (int)(mhi - mlo + 1);
+  const int64_t mm = a.m - 1;
+  const cd* ur = a.ubar + row * a.m;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) us[i] = ur[(mlo + i) & mm];
+  __syncthreads();
+  for (int q = threadIdx.x; q < a.ns; q += blockDim.x) {
+    const int64_t n = nb + q;
+    const int64_t lo = (n - a.mf_half >= 0) ? (n - a.mf_half + a.sps - 1) / a.sps
+                                            : -((a.mf_half - n) / a.sps);
+    const int64_t hi = (n + a.mf_half) / a.sps;
+    cd acc{0.0, 0.0};
+    for (int64_t m = lo; m <= hi; ++m) {
+      const double gj = a.mf[a.sps * m - n + a.mf_half];
+      const cd u = us[m - mlo];
+      acc.re = fma(gj, u.re, acc.re);
+      acc.im = fma(gj, u.im, acc.im);
+    }
+    store_c64(a.grad + row * a.n + n, acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_fwd(int n_pol, const FwdArgs& a, int threads, size_t lds, hipStream_t st) {
+  const unsigned blocks = (unsigned)(a.batch * a.tiles);
+  if (n_pol == 1)
+    hipLaunchKernelGGL(ldbp_fwd<1>, dim3(blocks), dim3(threads), lds, st, a, a.taps15, a.xi);
+  else
+    hipLaunchKernelGGL(ldbp_fwd<2>, dim3(blocks), dim3(threads), lds, st, a, a.taps15, a.xi);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd(int n_pol, const BwdArgs& a, int threads, size_t lds, hipStream_t st) {
+  const unsigned blocks = (unsigned)(a.batch * a.tiles);
+  if (n_pol == 1)
+    hipLaunchKernelGGL(ldbp_bwd<1>, dim3(blocks), dim3(threads), lds, st, a, a.taps15, a.xi);
+  else
+    hipLaunchKernelGGL(ldbp_bwd<2>, dim3(blocks), dim3(threads), lds, st, a, a.taps15, a.xi);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(const LossArgs& a, int64_t rows, hipStream_t st) {
+  const size_t lds = (size_t)(a.sps * (a.ms - 1) + 2 * a.mf_half + 1) * sizeof(float2);
+  hipLaunchKernelGGL(ldbp_loss, dim3((unsigned)(rows * a.tiles)), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_total(const double* partial, int count, double inv_count, double* loss,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(ldbp_loss_total, dim3(1), dim3(256), 0, st, partial, count, inv_count, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mf_adjoint(const MfAdjArgs& a, int64_t rows, hipStream_t st) {
+  const size_t lds = (size_t)((a.ns + 2 * a.mf_half) / a.sps + 3) * sizeof(cd);
+  hipLaunchKernelGGL(ldbp_mf_adjoint, dim3((unsigned)(rows * a.tiles)), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_taps(const cd* taps, int n_steps, int n_taps, cd* taps15, hipStream_t st) {
+  const int total = n_steps * TAPS;
+  hipLaunchKernelGGL(ldbp_pad_taps, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, taps,
+                     n_steps, n_taps, taps15);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, int blocks, int n_steps, int n_taps,
+                         cd* grad_taps, double* grad_xi, hipStream_t st) {
+  hipLaunchKernelGGL(ldbp_reduce, dim3((unsigned)n_steps), dim3(256), 0, st, partial, blocks,
+                     n_taps, grad_taps, grad_xi);
+  return hipGetLastError();
+}
+
+hipError_t prepare(int n_pol, size_t fwd_lds, size_t bwd_lds) {
+  hipError_t e = hipSuccess;
+  const void* f = n_pol == 1 ? reinterpret_cast<const void*>(&ldbp_fwd<1>)
+                             : reinterpret_cast<const void*>(&ldbp_fwd<2>);
+  const void* b = n_pol == 1 ? reinterpret_cast<const void*>(&ldbp_bwd<1>)
+                             : reinterpret_cast<const void*>(&ldbp_bwd<2>);
+  if (fwd_lds > 65536) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds);
+  if (e == hipSuccess && bwd_lds > 65536)
+    e = hipFuncSetAttribute(b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd_lds);
+  return e;
+}
+
+}  // namespace ldbp
+}  // namespace ssfm

@@ -14,15 +14,18 @@
 #include <vector>
 
 #include "ssfm.h"
+#include "host_common.hpp"
 #include "ssfm_internal.hpp"
 
 using ssfm::cd;
 
+namespace ssfm {
+
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-int fail(int code, const char* fmt, ...) {
+int api_fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -32,30 +35,26 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-int fail_hip(hipError_t e, const char* what) {
-  return fail(SSFM_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+int api_fail_hip(hipError_t e, const char* what) {
+  return api_fail(SSFM_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
+
+const std::string& api_last_error() { return g_last_error; }
+void api_clear_error() { g_last_error.clear(); }
+
+}  // namespace ssfm
+
+namespace {
+
+using ssfm::DeviceGuard;
+using ssfm::api_fail;
+using ssfm::api_fail_hip;
 
 constexpr double kPlanck = 6.62607015e-34;      // J s
 constexpr double kDefaultCarrier = 193.4145e12;  // Hz (1550 nm)
 constexpr double kPi = 3.14159265358979323846;
 
 bool finite(double v) { return isfinite(v) != 0; }
-
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-  int prev = -1;
-  hipError_t status = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    status = hipGetDevice(&prev);
-    if (status == hipSuccess && prev != dev) status = hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
 }  // namespace
 
 struct ssfm_plan_s {
@@ -122,29 +121,29 @@ struct ssfm_plan_s {
 namespace {
 
 int validate_link(const ssfm_link* l) {
-  if (!l) return fail(SSFM_EINVAL, "link is NULL");
-  if (l->n_pol != 1 && l->n_pol != 2) return fail(SSFM_EINVAL, "n_pol must be 1 or 2, got %d", l->n_pol);
+  if (!l) return api_fail(SSFM_EINVAL, "link is NULL");
+  if (l->n_pol != 1 && l->n_pol != 2) return api_fail(SSFM_EINVAL, "n_pol must be 1 or 2, got %d", l->n_pol);
   const int64_t n = l->n_samples;
   if (n < 64 || n > (int64_t(1) << 18) || (n & (n - 1)) != 0)
-    return fail(SSFM_EINVAL, "n_samples must be a power of two in [2^6, 2^18], got %lld",
+    return api_fail(SSFM_EINVAL, "n_samples must be a power of two in [2^6, 2^18], got %lld",
                 (long long)n);
   if (l->n_spans < 1 || l->n_spans > 65535)
-    return fail(SSFM_EINVAL, "n_spans must be in [1, 65535], got %d", l->n_spans);
+    return api_fail(SSFM_EINVAL, "n_spans must be in [1, 65535], got %d", l->n_spans);
   if (l->steps_per_span < 1 || l->steps_per_span > (1 << 24))
-    return fail(SSFM_EINVAL, "steps_per_span must be in [1, 2^24], got %d", l->steps_per_span);
-  if (l->ase != 0 && l->ase != 1) return fail(SSFM_EINVAL, "ase must be 0 or 1");
+    return api_fail(SSFM_EINVAL, "steps_per_span must be in [1, 2^24], got %d", l->steps_per_span);
+  if (l->ase != 0 && l->ase != 1) return api_fail(SSFM_EINVAL, "ase must be 0 or 1");
   if (!finite(l->sample_rate_hz) || l->sample_rate_hz <= 0)
-    return fail(SSFM_EINVAL, "sample_rate_hz must be finite and > 0");
-  if (!finite(l->span_km) || l->span_km <= 0) return fail(SSFM_EINVAL, "span_km must be finite and > 0");
+    return api_fail(SSFM_EINVAL, "sample_rate_hz must be finite and > 0");
+  if (!finite(l->span_km) || l->span_km <= 0) return api_fail(SSFM_EINVAL, "span_km must be finite and > 0");
   if (!finite(l->alpha_db_per_km) || !finite(l->beta2_ps2_per_km) || !finite(l->gamma_per_w_km))
-    return fail(SSFM_EINVAL, "alpha, beta2 and gamma must be finite");
+    return api_fail(SSFM_EINVAL, "alpha, beta2 and gamma must be finite");
   if (!finite(l->nl_factor) && !isnan(l->nl_factor))
-    return fail(SSFM_EINVAL, "nl_factor must be finite or NaN");
-  if (!finite(l->edfa_gain_db)) return fail(SSFM_EINVAL, "edfa_gain_db must be finite");
-  if (l->ase && !finite(l->edfa_nf_db)) return fail(SSFM_EINVAL, "edfa_nf_db must be finite");
+    return api_fail(SSFM_EINVAL, "nl_factor must be finite or NaN");
+  if (!finite(l->edfa_gain_db)) return api_fail(SSFM_EINVAL, "edfa_gain_db must be finite");
+  if (l->ase && !finite(l->edfa_nf_db)) return api_fail(SSFM_EINVAL, "edfa_nf_db must be finite");
   if (!isnan(l->carrier_hz) && (!finite(l->carrier_hz) || l->carrier_hz <= 0))
-    return fail(SSFM_EINVAL, "carrier_hz must be NaN or finite and > 0");
-  if (l->flags != 0 || l->reserved != 0) return fail(SSFM_EINVAL, "flags and reserved must be 0");
+    return api_fail(SSFM_EINVAL, "carrier_hz must be NaN or finite and > 0");
+  if (l->flags != 0 || l->reserved != 0) return api_fail(SSFM_EINVAL, "flags and reserved must be 0");
   return SSFM_OK;
 }
 
@@ -183,12 +182,12 @@ int upload(ssfm_plan_s* p, T** dst, const std::vector<T>& src) {
   const size_t bytes = src.size() * sizeof(T);
   void* d = nullptr;
   if (getenv("SSFM_FAIL_ALLOC") && strcmp(getenv("SSFM_FAIL_ALLOC"), "1") == 0)
-    return fail(SSFM_ENOMEM, "allocation failure injected by SSFM_FAIL_ALLOC=1");
+    return api_fail(SSFM_ENOMEM, "allocation failure injected by SSFM_FAIL_ALLOC=1");
   hipError_t e = hipMalloc(&d, bytes);
-  if (e != hipSuccess) return fail(SSFM_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  if (e != hipSuccess) return api_fail(SSFM_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
   p->allocations.push_back(d);
   e = hipMemcpy(d, src.data(), bytes, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return fail_hip(e, "hipMemcpy (plan tables)");
+  if (e != hipSuccess) return api_fail_hip(e, "hipMemcpy (plan tables)");
   *dst = static_cast<T*>(d);
   p->table_bytes += bytes;
   return SSFM_OK;
@@ -335,7 +334,7 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
     a.realization0 = real0;
     a.seeds = seeds;
     if ((e = launch(p, KIND_LDS, field_bytes, st, [&] { return ks.lds(a, batch, st); })) != hipSuccess)
-      return fail_hip(e, "k1_lds launch");
+      return api_fail_hip(e, "k1_lds launch");
     return SSFM_OK;
   }
   bool wide = false;
@@ -364,14 +363,14 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
   a.seeds = seeds;
   if ((e = launch(p, KIND_COL, field_bytes, st,
                   [&] { return cols.col[ssfm::MODE_FIRST](a, batch, st); })) != hipSuccess)
-    return fail_hip(e, "k3 launch");
+    return api_fail_hip(e, "k3 launch");
   for (int s = s0; s < s1; ++s) {
     a.span = s;
     for (int i = 0; i <= p->steps; ++i) {
       ra.H = (i == 0 || i == p->steps) ? p->h_half : p->h_full;
       if ((e = launch(p, KIND_ROW, field_bytes, st,
                       [&] { return row(ra, rows, st); })) != hipSuccess)
-        return fail_hip(e, "k2 launch");
+        return api_fail_hip(e, "k2 launch");
       int mode;
       if (i < p->steps) {
         mode = ssfm::MODE_NL;
@@ -382,21 +381,21 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
       }
       if ((e = launch(p, KIND_COL, field_bytes, st,
                       [&] { return cols.col[mode](a, batch, st); })) != hipSuccess)
-        return fail_hip(e, "k3 launch");
+        return api_fail_hip(e, "k3 launch");
     }
   }
   return SSFM_OK;
 }
 
 int check_call(ssfm_plan_t plan, const void* field, int64_t batch) {
-  if (!plan) return fail(SSFM_EINVAL, "plan is NULL");
-  if (!field) return fail(SSFM_EINVAL, "field is NULL");
-  if (((uintptr_t)field & 7u) != 0) return fail(SSFM_EINVAL, "field must be 8-byte aligned");
-  if (batch < 1) return fail(SSFM_EINVAL, "batch must be >= 1, got %lld", (long long)batch);
+  if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
+  if (!field) return api_fail(SSFM_EINVAL, "field is NULL");
+  if (((uintptr_t)field & 7u) != 0) return api_fail(SSFM_EINVAL, "field must be 8-byte aligned");
+  if (batch < 1) return api_fail(SSFM_EINVAL, "batch must be >= 1, got %lld", (long long)batch);
   const int64_t n2 = plan->ks.path == 2 ? plan->ks.n2 : 1;
   const int64_t cols = plan->ks.path == 2 ? plan->ks.narrow.columns : 1;
   if (batch * (n2 / cols) > 0x7fffffff || batch * plan->n_pol * plan->ks.n1 > (int64_t(1) << 40))
-    return fail(SSFM_EINVAL, "batch %lld exceeds the launch grid", (long long)batch);
+    return api_fail(SSFM_EINVAL, "batch %lld exceeds the launch grid", (long long)batch);
   return SSFM_OK;
 }
 
@@ -454,21 +453,21 @@ int cached_plan(const ssfm_link& key, int device, ssfm_plan_t* out) {
 extern "C" {
 
 int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out) {
-  g_last_error.clear();
-  if (!out) return fail(SSFM_EINVAL, "out is NULL");
+  ssfm::api_clear_error();
+  if (!out) return api_fail(SSFM_EINVAL, "out is NULL");
   *out = nullptr;
   int rc = validate_link(link);
   if (rc != SSFM_OK) return rc;
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);
-  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceCount");
+  if (e != hipSuccess) return api_fail_hip(e, "hipGetDeviceCount");
   if (hip_device < 0 || hip_device >= count)
-    return fail(SSFM_EINVAL, "hip_device %d out of range (%d devices)", hip_device, count);
+    return api_fail(SSFM_EINVAL, "hip_device %d out of range (%d devices)", hip_device, count);
   DeviceGuard guard(hip_device);
-  if (guard.status != hipSuccess) return fail_hip(guard.status, "hipSetDevice");
+  if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
 
   ssfm_plan_s* p = new (std::nothrow) ssfm_plan_s();
-  if (!p) return fail(SSFM_ENOMEM, "host allocation of the plan failed");
+  if (!p) return api_fail(SSFM_ENOMEM, "host allocation of the plan failed");
   p->link = *link;
   p->device = hip_device;
   p->n_pol = link->n_pol;
@@ -477,12 +476,12 @@ int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out) {
   p->spans = link->n_spans;
   if (!ssfm::select_kernels(p->n, p->n_pol, p->ks)) {
     delete p;
-    return fail(SSFM_EUNSUPPORTED, "no kernel for n_samples = %lld", (long long)link->n_samples);
+    return api_fail(SSFM_EUNSUPPORTED, "no kernel for n_samples = %lld", (long long)link->n_samples);
   }
   if (p->ks.prepare != hipSuccess) {
     const hipError_t pe = p->ks.prepare;
     delete p;
-    return fail_hip(pe, "hipFuncSetAttribute (LDS size)");
+    return api_fail_hip(pe, "hipFuncSetAttribute (LDS size)");
   }
   rc = build_tables(p);
   if (rc != SSFM_OK) {
@@ -501,7 +500,7 @@ int ssfm_plan_destroy(ssfm_plan_t plan) {
 }
 
 int ssfm_plan_get_info(ssfm_plan_t plan, ssfm_plan_info* info) {
-  if (!plan || !info) return fail(SSFM_EINVAL, "plan and info must be non-NULL");
+  if (!plan || !info) return api_fail(SSFM_EINVAL, "plan and info must be non-NULL");
   info->path = plan->ks.path;
   info->n1 = plan->ks.path == 2 ? plan->ks.n1 : 0;
   info->n2 = plan->ks.path == 2 ? plan->ks.n2 : 0;
@@ -514,14 +513,14 @@ int ssfm_plan_get_info(ssfm_plan_t plan, ssfm_plan_info* info) {
 int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch, uint64_t seed,
                        uint64_t realization0, int32_t span_begin, int32_t span_end,
                        void* stream) {
-  g_last_error.clear();
+  ssfm::api_clear_error();
   int rc = check_call(plan, field, batch);
   if (rc != SSFM_OK) return rc;
   if (span_begin < 0 || span_end < span_begin || span_end > plan->spans)
-    return fail(SSFM_EINVAL, "span range [%d, %d) outside [0, %d]", span_begin, span_end,
+    return api_fail(SSFM_EINVAL, "span range [%d, %d) outside [0, %d]", span_begin, span_end,
                 plan->spans);
   DeviceGuard guard(plan->device);
-  if (guard.status != hipSuccess) return fail_hip(guard.status, "hipSetDevice");
+  if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!use_graphs(plan))
     return run_forward(plan, static_cast<float2*>(field), batch, seed, realization0, span_begin,
@@ -552,10 +551,10 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch, uint64_t se
     hipError_t e;
     if (!plan->capture_stream &&
         (e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking)) != hipSuccess)
-      return fail_hip(e, "hipStreamCreate (capture)");
+      return api_fail_hip(e, "hipStreamCreate (capture)");
     if ((e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal)) !=
         hipSuccess)
-      return fail_hip(e, "hipStreamBeginCapture");
+      return api_fail_hip(e, "hipStreamBeginCapture");
     const int rc2 = run_forward(plan, static_cast<float2*>(field), batch, seed, realization0,
                                 span_begin, span_end, plan->capture_stream);
     hipGraph_t graph = nullptr;
@@ -564,36 +563,36 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch, uint64_t se
       if (graph) (void)hipGraphDestroy(graph);
       return rc2;
     }
-    if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+    if (e != hipSuccess) return api_fail_hip(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
       plan->graph_exec = nullptr;
-      return fail_hip(e, "hipGraphInstantiate");
+      return api_fail_hip(e, "hipGraphInstantiate");
     }
     plan->graph_valid = true;
   }
   const hipError_t e = hipGraphLaunch(plan->graph_exec, st);
-  if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+  if (e != hipSuccess) return api_fail_hip(e, "hipGraphLaunch");
   return SSFM_OK;
 }
 
 int ssfm_forward(ssfm_plan_t plan, void* field, int64_t batch, uint64_t seed, void* stream) {
-  if (!plan) return fail(SSFM_EINVAL, "plan is NULL");
+  if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
   return ssfm_forward_spans(plan, field, batch, seed, 0, 0, plan->spans, stream);
 }
 
 int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t batch,
                  uint64_t seed, void* stream) {
-  g_last_error.clear();
+  ssfm::api_clear_error();
   int rc = check_call(plan, field_in, batch);
   if (rc != SSFM_OK) return rc;
-  if (!grad) return fail(SSFM_EINVAL, "grad is NULL");
-  if (((uintptr_t)grad & 7u) != 0) return fail(SSFM_EINVAL, "grad must be 8-byte aligned");
+  if (!grad) return api_fail(SSFM_EINVAL, "grad is NULL");
+  if (((uintptr_t)grad & 7u) != 0) return api_fail(SSFM_EINVAL, "grad must be 8-byte aligned");
   if (plan->ks.path != 2)
-    return fail(SSFM_EUNSUPPORTED, "ssfm_adjoint needs n_samples >= 2^14 (four-step path)");
+    return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint needs n_samples >= 2^14 (four-step path)");
   DeviceGuard guard(plan->device);
-  if (guard.status != hipSuccess) return fail_hip(guard.status, "hipSetDevice");
+  if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const ssfm::KernelSet& ks = plan->ks;
   const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
@@ -610,7 +609,7 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
         hipMalloc(&plan->adj_work, work_bytes) != hipSuccess) {
       if (plan->adj_ckpt) (void)hipFree(plan->adj_ckpt);
       plan->adj_ckpt = nullptr;
-      return fail(SSFM_ENOMEM, "adjoint workspace of %zu bytes", ckpt_bytes + work_bytes);
+      return api_fail(SSFM_ENOMEM, "adjoint workspace of %zu bytes", ckpt_bytes + work_bytes);
     }
     plan->adj_ckpt_bytes = ckpt_bytes;
     plan->adj_work_bytes = work_bytes;
@@ -620,12 +619,12 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
   // forward pass on a copy of the input, keeping the span-end states
   if ((e = hipMemcpyAsync(work, field_in, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
-    return fail_hip(e, "hipMemcpyAsync (adjoint input)");
+    return api_fail_hip(e, "hipMemcpyAsync (adjoint input)");
   rc = run_forward(plan, work, batch, seed, 0, 0, plan->spans, st, plan->adj_ckpt);
   if (rc != SSFM_OK) return rc;
   if ((e = hipMemcpyAsync(cot, grad, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
-    return fail_hip(e, "hipMemcpyAsync (cotangent)");
+    return api_fail_hip(e, "hipMemcpyAsync (cotangent)");
 
   // reverse sweep: state and cotangent together, span by span
   const int64_t batch2 = 2 * batch;
@@ -655,48 +654,48 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
     aa.ckpt = plan->adj_ckpt + (size_t)s * slice;
     if ((e = launch(plan, KIND_ADJ, row_bytes, st,
                     [&] { return ks.adj[ssfm::AMODE_FIRST](aa, st); })) != hipSuccess)
-      return fail_hip(e, "k3_adj launch");
+      return api_fail_hip(e, "k3_adj launch");
     for (int i = plan->steps; i >= 0; --i) {
       ra.H = (i == 0 || i == plan->steps) ? plan->h_half : plan->h_full;
       if ((e = launch(plan, KIND_ROW, row_bytes, st, [&] { return row(ra, rows, st); })) !=
           hipSuccess)
-        return fail_hip(e, "k2 launch");
+        return api_fail_hip(e, "k2 launch");
       if (i > 0) {
         aa.kappa = plan->kappa[(size_t)(i - 1)];
         if ((e = launch(plan, KIND_ADJ, row_bytes, st,
                         [&] { return ks.adj[ssfm::AMODE_NL](aa, st); })) != hipSuccess)
-          return fail_hip(e, "k3_adj launch");
+          return api_fail_hip(e, "k3_adj launch");
       }
     }
     if ((e = launch(plan, KIND_ADJ, row_bytes, st,
                     [&] { return ks.adj[ssfm::AMODE_LAST](aa, st); })) != hipSuccess)
-      return fail_hip(e, "k3_adj launch");
+      return api_fail_hip(e, "k3_adj launch");
   }
   if ((e = hipMemcpyAsync(grad, cot, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
-    return fail_hip(e, "hipMemcpyAsync (gradient)");
+    return api_fail_hip(e, "hipMemcpyAsync (gradient)");
   return SSFM_OK;
 }
 
 int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
                const uint64_t* seeds, int hip_device, void* stream) {
-  g_last_error.clear();
-  if (!links || !fields || !seeds) return fail(SSFM_EINVAL, "links, fields and seeds must be non-NULL");
-  if (count < 1) return fail(SSFM_EINVAL, "count must be >= 1");
+  ssfm::api_clear_error();
+  if (!links || !fields || !seeds) return api_fail(SSFM_EINVAL, "links, fields and seeds must be non-NULL");
+  if (count < 1) return api_fail(SSFM_EINVAL, "count must be >= 1");
   for (int64_t i = 0; i < count; ++i) {
     int rc = validate_link(&links[i]);
     if (rc != SSFM_OK) return rc;
-    if (!fields[i]) return fail(SSFM_EINVAL, "fields[%lld] is NULL", (long long)i);
+    if (!fields[i]) return api_fail(SSFM_EINVAL, "fields[%lld] is NULL", (long long)i);
     if (((uintptr_t)fields[i] & 7u) != 0)
-      return fail(SSFM_EINVAL, "fields[%lld] must be 8-byte aligned", (long long)i);
+      return api_fail(SSFM_EINVAL, "fields[%lld] must be 8-byte aligned", (long long)i);
   }
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
-  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceCount");
+  if (e != hipSuccess) return api_fail_hip(e, "hipGetDeviceCount");
   if (hip_device < 0 || hip_device >= ndev)
-    return fail(SSFM_EINVAL, "hip_device %d out of range (%d devices)", hip_device, ndev);
+    return api_fail(SSFM_EINVAL, "hip_device %d out of range (%d devices)", hip_device, ndev);
   DeviceGuard guard(hip_device);
-  if (guard.status != hipSuccess) return fail_hip(guard.status, "hipSetDevice");
+  if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
 
   // group by physical link (the span count is per entry: plans do not depend
@@ -729,11 +728,11 @@ int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
     void* stage = nullptr;
     void* dseeds = nullptr;
     if ((e = hipMallocAsync(&stage, (size_t)m * fbytes, st)) != hipSuccess)
-      return fail(SSFM_ENOMEM, "staging buffer of %zu bytes: %s", (size_t)m * fbytes,
+      return api_fail(SSFM_ENOMEM, "staging buffer of %zu bytes: %s", (size_t)m * fbytes,
                   hipGetErrorString(e));
     if ((e = hipMallocAsync(&dseeds, (size_t)m * sizeof(uint64_t), st)) != hipSuccess) {
       (void)hipFreeAsync(stage, st);
-      return fail(SSFM_ENOMEM, "seed buffer: %s", hipGetErrorString(e));
+      return api_fail(SSFM_ENOMEM, "seed buffer: %s", hipGetErrorString(e));
     }
     std::vector<uint64_t> hseeds((size_t)m);
     for (int64_t r = 0; r < m; ++r) {
@@ -762,13 +761,13 @@ int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
     (void)hipFreeAsync(stage, st);
     (void)hipFreeAsync(dseeds, st);
     if (rc != SSFM_OK) return rc;
-    if (e != hipSuccess) return fail_hip(e, "ssfm_batch copies");
+    if (e != hipSuccess) return api_fail_hip(e, "ssfm_batch copies");
   }
   return SSFM_OK;
 }
 
 int ssfm_profile_begin(ssfm_plan_t plan) {
-  if (!plan) return fail(SSFM_EINVAL, "plan is NULL");
+  if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
   plan->profiling = true;
   plan->events_used = 0;
   plan->prof_kind.clear();
@@ -777,7 +776,7 @@ int ssfm_profile_begin(ssfm_plan_t plan) {
 }
 
 int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int* count) {
-  if (!plan || !out || !count) return fail(SSFM_EINVAL, "plan, out and count must be non-NULL");
+  if (!plan || !out || !count) return api_fail(SSFM_EINVAL, "plan, out and count must be non-NULL");
   plan->profiling = false;
   DeviceGuard guard(plan->device);
   double ms[KIND_COUNT] = {0, 0, 0, 0}, bytes[KIND_COUNT] = {0, 0, 0, 0};
@@ -785,12 +784,12 @@ int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int
   const size_t launches = plan->prof_kind.size();
   if (launches) {
     hipError_t e = hipEventSynchronize(plan->events[2 * launches - 1]);
-    if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+    if (e != hipSuccess) return api_fail_hip(e, "hipEventSynchronize");
   }
   for (size_t i = 0; i < launches; ++i) {
     float t = 0.0f;
     hipError_t e = hipEventElapsedTime(&t, plan->events[2 * i], plan->events[2 * i + 1]);
-    if (e != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
+    if (e != hipSuccess) return api_fail_hip(e, "hipEventElapsedTime");
     const int k = plan->prof_kind[i];
     ms[k] += t;
     bytes[k] += plan->prof_bytes[i];
@@ -824,7 +823,7 @@ const char* ssfm_status_string(int status) {
   }
 }
 
-const char* ssfm_last_error(void) { return g_last_error.c_str(); }
+const char* ssfm_last_error(void) { return ssfm::api_last_error().c_str(); }
 
 int ssfm_version(void) { return 100; }
 

@@ -1,6 +1,7 @@
-"""The C-ABI library: it loads, exports what include/ssfm.h declares, and
+"""The C-ABI library: it loads, exports what include/*.h declare, and
 rejects invalid arguments before touching a device (runs without a GPU)."""
 
+import glob
 import math
 import os
 import re
@@ -8,7 +9,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ssfm.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 ssfm = pytest.importorskip("paper_2507_03509_amd")
 
@@ -17,7 +18,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(ssfm.library_path()),
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(ssfm_\w+)\s*\(", text, re.M)))
 
@@ -25,7 +26,8 @@ def declared_functions():
 def test_header_declares_the_abi():
     names = declared_functions()
     for need in ("ssfm_plan", "ssfm_forward", "ssfm_adjoint", "ssfm_batch",
-                 "ssfm_plan_destroy", "ssfm_status_string"):
+                 "ssfm_plan_destroy", "ssfm_status_string", "ssfm_ldbp_create",
+                 "ssfm_ldbp_forward", "ssfm_ldbp_loss", "ssfm_ldbp_backward"):
         assert need in names
 
 
@@ -105,3 +107,63 @@ def test_batch_entry_validates_each_link():
 def test_binding_rejects_non_tensor_fields():
     with pytest.raises(TypeError):
         ssfm._field_args([1, 2, 3])
+
+
+def test_ldbp_desc_layout():
+    import ctypes
+    from paper_2507_03509_amd import ldbp
+    # 4 int32, int64, 2 int32
+    assert ctypes.sizeof(ldbp.SsfmLdbpDesc) == 32
+    assert ldbp.SsfmLdbpDesc.n_samples.offset == 16
+    assert ldbp.SsfmLdbpDesc.mf_taps.offset == 28
+
+
+def _ldbp_good(**kw):
+    from paper_2507_03509_amd import ldbp
+    base = dict(n_pol=2, n_steps=20, n_taps=15, steps_per_span=2, n_samples=1 << 14, sps=2,
+                mf_taps=129)
+    base.update(kw)
+    return ldbp.SsfmLdbpDesc(**base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_pol=0), dict(n_pol=3), dict(n_steps=0), dict(n_steps=5000), dict(n_taps=0),
+    dict(n_taps=14), dict(n_taps=17), dict(steps_per_span=0), dict(steps_per_span=5),
+    dict(steps_per_span=3), dict(n_samples=1000), dict(n_samples=32), dict(n_samples=1 << 23),
+    dict(sps=0), dict(sps=3), dict(sps=128), dict(mf_taps=0), dict(mf_taps=128),
+    dict(mf_taps=259),
+])
+def test_invalid_ldbp_descriptions_are_rejected_without_a_device(bad):
+    from paper_2507_03509_amd import ldbp
+    with pytest.raises(ssfm.SsfmError) as e:
+        ldbp.ssfm_ldbp_create(_ldbp_good(**bad), 0)
+    assert e.value.status == ssfm.SSFM_EINVAL
+    assert ssfm.ssfm_last_error()
+
+
+def test_ldbp_null_handle_is_rejected():
+    from paper_2507_03509_amd import ldbp
+    with pytest.raises(ssfm.SsfmError) as e:
+        ldbp.ssfm_ldbp_forward(None, 8, 16, 24, 32, 1, None, None)
+    assert e.value.status == ssfm.SSFM_EINVAL
+    with pytest.raises(ssfm.SsfmError) as e:
+        ldbp.ssfm_ldbp_checkpoint_bytes(None, 1)
+    assert e.value.status == ssfm.SSFM_EINVAL
+
+
+def test_ldbp_init_params_match_the_oracle():
+    # the binding's host-side initialisation against the oracle's (written
+    # independently from the same definition)
+    import numpy as np
+    import oracle
+    from paper_2507_03509_amd import ldbp
+    from workloads import LDBP, Link
+    links = [LDBP.workload.link,
+             Link(n_pol=1, n_samples=256, sample_rate_hz=32e9, span_km=60.0, n_spans=3,
+                  steps_per_span=4, alpha_db_per_km=0.25, beta2_ps2_per_km=-20.0,
+                  gamma_per_w_km=1.1, edfa_gain_db=12.0)]
+    for ln, t, s in [(links[0], 15, 2), (links[1], 9, 4), (links[1], 1, 1)]:
+        ta, xa = ldbp.init_params(ln, t, s)
+        tb, xb = oracle.init_params(ln, t, s)
+        np.testing.assert_allclose(ta, tb, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(xa, xb, rtol=1e-12, atol=0)

@@ -8,12 +8,14 @@ propagation arithmetic: no dispersion, nonlinearity, amplifier or noise model
 lives here, so the oracle and the GPU path stay independent of each other.
 """
 
-from .configs import Link, CONFIGS, config_link, BatchItem, batch_config
-from .signals import (qam16_symbols, rrc_response, shaped_field,
-                      dual_pol_field, wdm_field, make_field, dbm_to_watt)
+from .configs import Link, CONFIGS, config_link, BatchItem, batch_config, LdbpConfig, LDBP
+from .signals import (qam16_symbols, rrc_response, rrc_taps, shaped_field,
+                      dual_pol_field, wdm_field, make_field, dbm_to_watt,
+                      field_and_targets)
 
 __all__ = [
     "Link", "CONFIGS", "config_link", "BatchItem", "batch_config",
-    "qam16_symbols", "rrc_response", "shaped_field", "dual_pol_field",
-    "wdm_field", "make_field", "dbm_to_watt",
+    "qam16_symbols", "rrc_response", "rrc_taps", "shaped_field",
+    "dual_pol_field", "wdm_field", "make_field", "dbm_to_watt",
+    "field_and_targets", "LdbpConfig", "LDBP",
 ]

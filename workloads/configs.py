@@ -159,3 +159,24 @@ def batch_config(n: int = 256, seed: int = 20250703 + 4,
     return [BatchItem(n_samples=int(ln[i]), launch_dbm=float(p[i]),
                       n_spans=int(spans[i]), seed=4000 + i,
                       symbol_seed=seed * 1000 + i) for i in range(n)]
+
+
+@dataclass(frozen=True)
+class LdbpConfig:
+    """Workload 5's learned back-propagation: ``batch`` received fields of
+    the workload-5 link, K = n_spans * steps_per_span FIR + Kerr steps of
+    ``n_taps`` taps, loss through a ``2 mf_half + 1``-tap RRC matched filter
+    at the workload's samples per symbol."""
+
+    workload: Workload
+    batch: int = 64
+    n_taps: int = 15
+    steps_per_span: int = 2
+    mf_half: int = 64
+
+    @property
+    def n_steps(self) -> int:
+        return self.workload.link.n_spans * self.steps_per_span
+
+
+LDBP = LdbpConfig(workload=CONFIGS[5])

@@ -14,7 +14,8 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["dbm_to_watt", "qam16_symbols", "rrc_response", "rrc_taps",
-           "shaped_field", "dual_pol_field", "wdm_field", "make_field"]
+           "shaped_field", "dual_pol_field", "wdm_field", "make_field",
+           "field_and_targets"]
 
 
 def dbm_to_watt(p_dbm: float) -> float:
@@ -93,6 +94,30 @@ def dual_pol_field(rng: np.random.Generator, n_pol: int, n_samples: int,
     a = np.stack([shaped_field(qam16_symbols(rng, m), sps, symbol_rate, rolloff)
                   for _ in range(n_pol)])
     return _normalise(a, dbm_to_watt(launch_dbm))
+
+
+def field_and_targets(rng: np.random.Generator, n_pol: int, n_samples: int,
+                      sps: int, symbol_rate: float, rolloff: float,
+                      launch_dbm: float, mf: np.ndarray):
+    """Single-carrier field (as ``dual_pol_field``) and its symbols in field
+    units: each polarisation's symbols times the power normalisation of that
+    polarisation and the gain of the real matched filter ``mf`` (2R + 1 taps)
+    on one shaped pulse, so that the matched filter sampled at the symbol
+    instants returns the targets up to intersymbol interference.  Returns
+    (field [P, N], targets [P, N / sps])."""
+    if n_samples % sps:
+        raise ValueError("n_samples must be a multiple of sps")
+    m = n_samples // sps
+    syms = np.stack([qam16_symbols(rng, m) for _ in range(n_pol)])
+    raw = np.stack([shaped_field(syms[p], sps, symbol_rate, rolloff) for p in range(n_pol)])
+    pw = np.mean(np.abs(raw) ** 2, axis=-1, keepdims=True)
+    scale = np.sqrt((dbm_to_watt(launch_dbm) / n_pol) / pw)
+    impulse = np.zeros(m, dtype=np.complex128)
+    impulse[0] = 1.0
+    pulse = shaped_field(impulse, sps, symbol_rate, rolloff)
+    r = (len(mf) - 1) // 2
+    gain = sum(mf[j + r] * pulse[(-j) % n_samples] for j in range(-r, r + 1))
+    return raw * scale, syms * scale * gain
 
 
 def wdm_field(rng: np.random.Generator, n_pol: int, n_samples: int,
