@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=512)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4],
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="2: Manakov 2^16 link over a batch; 4: 256 mixed realisations "
                          "(ssfm_batch against the one-at-a-time loop)")
     ap.add_argument("--single-steps", type=int, default=3,
@@ -172,10 +172,138 @@ def bench_mixed_batch(args) -> int:
     return 0
 
 
+def bench_ldbp(args) -> int:
+    """Workload 5: learned digital back-propagation over 64 received dual-pol
+    fields of 2^14 samples (10 x 80 km, 2 steps per span, 15 taps).  A
+    training step is forward with span checkpoints, matched-filter MSE with
+    its gradient, and the backward pass; its time is compared with the
+    forward-and-loss time (fwd+adjoint / fwd)."""
+    import numpy as np
+    import torch
+
+    import paper_2507_03509_amd as ssfm
+    from paper_2507_03509_amd import ldbp
+    from workloads import LDBP, field_and_targets, rrc_taps
+
+    ssfm.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = LDBP
+    w = cfg.workload
+    ln = w.link
+    B, P, N, K = cfg.batch, ln.n_pol, ln.n_samples, cfg.n_steps
+    mf = rrc_taps(w.sps, w.rolloff, cfg.mf_half)
+    rng = np.random.default_rng(w.symbol_seed)
+    tx, tg = [], []
+    for _ in range(B):
+        f, t = field_and_targets(rng, P, N, w.sps, w.symbol_rate_hz, w.rolloff, w.launch_dbm, mf)
+        tx.append(f)
+        tg.append(t)
+    # received fields: this library's own propagation over the link (untimed)
+    x = torch.from_numpy(np.stack(tx).astype(np.complex64)).to(dev)
+    plan = ssfm.Plan(ln, device=0)
+    plan.forward(x, seed=w.ase_seed)
+    sym = torch.from_numpy(np.stack(tg).astype(np.complex64)).to(dev)
+    mfd = torch.from_numpy(mf).to(dev)
+    taps_h, xi_h = ldbp.init_params(ln, cfg.n_taps, cfg.steps_per_span)
+    taps = torch.from_numpy(taps_h).to(dev)
+    xi = torch.from_numpy(xi_h).to(dev)
+    model = ldbp.Ldbp(n_pol=P, n_steps=K, n_taps=cfg.n_taps, steps_per_span=cfg.steps_per_span,
+                      n_samples=N, sps=w.sps, mf_taps=2 * cfg.mf_half + 1, device=0)
+    ck = model.new_checkpoints(B)
+    stream = torch.cuda.current_stream(dev)
+    state = {}
+
+    def fwd():
+        z = model.forward(x, taps, xi)
+        state["loss"], _ = model.loss(z, sym, mfd, want_grad=False)
+
+    def train():
+        z = model.forward(x, taps, xi, ck)
+        loss, g = model.loss(z, sym, mfd, want_grad=True)
+        state["grads"] = model.backward(x, z, taps, xi, ck, g)
+        state["loss"] = loss
+
+    def timed(fn, reps):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(10, 10 * args.steps)
+    ms_fwd = timed(fwd, reps)
+    ms_train = timed(train, reps)
+    # the forward kernel alone (one fused launch for K <= 20), for the roofline
+    ms_fwd_kernel = timed(lambda: model.forward(x, taps, xi), reps)
+    work = B * N * K                                   # sample-steps per pass
+    # algorithmic FP64 flops per sample-step: FIR 8 T per polarisation
+    # (T complex multiply-adds), Kerr 3 P (|y|^2) + 1 (phase) + 6 P (rotation);
+    # the phasor itself is not counted
+    flops = P * 8 * cfg.n_taps + 9 * P + 1
+    achieved = work * flops / (ms_fwd_kernel * 1e-3) / 1e12
+    peak = 78.6
+    value = work / (ms_train / 1e3)
+    log(f"LDBP {B} x {P} x 2^{int(math.log2(N))}, K={K}: forward+loss {ms_fwd:.3f} ms, "
+        f"train step {ms_train:.3f} ms ({ms_train / ms_fwd:.2f}x), forward kernel "
+        f"{ms_fwd_kernel:.3f} ms = {achieved:.1f} TFLOP/s FP64, loss {float(state['loss'][0]):.4e}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        x_h = x[:1].cpu().numpy().astype(np.complex128)
+        s_h = sym[:1].cpu().numpy().astype(np.complex128)
+        t0 = time.perf_counter()
+        done = 0
+        while True:
+            zo = oracle.ldbp_forward(x_h, taps_h, xi_h)
+            gzo = oracle.mse_grad(zo, s_h, mf, w.sps) / B   # loss normalised over the batch
+            oracle.ldbp_backward(x_h, taps_h, xi_h, gzo)
+            done += 1
+            if time.perf_counter() - t0 >= min(args.cpu_seconds, 30.0):
+                break
+        csec = time.perf_counter() - t0
+        cpu = {"value": done * N * K / csec, "unit": "sample-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{done} realisation(s) of 1 x {P} x {N}: forward, loss gradient "
+                         f"and backward in {csec:.1f} s"}
+        log(f"oracle training step: {done} realisation(s) in {csec:.1f} s")
+    out = {
+        "metric": "LDBP training step sample-steps/s (forward, MSE, backward) at <=1e-5 rel. error",
+        "value": value, "unit": "sample-steps/s", "n_gpus": 1, "steps": reps,
+        "warmup": max(1, args.warmup), "ms_per_step": round(ms_train, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"learned DBP: {B} x {P}-pol x {N} received fields, "
+                               f"{ln.n_spans} x {ln.span_km:g} km, {cfg.steps_per_span} "
+                               f"steps/span, {cfg.n_taps} taps, MSE through a "
+                               f"{2 * cfg.mf_half + 1}-tap RRC matched filter",
+                   "sample_steps_per_pass": work, "parallelism": "single-gpu"},
+        "ms_forward_and_loss": round(ms_fwd, 4), "ms_train_step": round(ms_train, 4),
+        "fwd_adjoint_over_fwd": round(ms_train / ms_fwd, 3),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "ldbp_fwd", "avg_launch_us": round(ms_fwd_kernel * 1e3, 2),
+                     "algorithmic_flops_per_launch": work * flops},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    model.close()
+    plan.close()
+    return 0
+
+
 def main() -> int:
     args = parse()
     if args.workload == 4 and args.gpus == 1:
         return bench_mixed_batch(args)
+    if args.workload == 5 and args.gpus == 1:
+        return bench_ldbp(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the SSFM "
               "path has no multi-GPU code", file=sys.stderr)

@@ -104,7 +104,7 @@ struct ssfm_ldbp_s {
     const int s = d.steps_per_span;
     const int halo = L::HC * std::max(s, 2 * (s - 1));
     Geometry g = make_geometry(d.n_samples, bwd_tile, halo, s + 1, d.n_pol, 0);
-    g.lds += (size_t)(g.threads / 64) * L::NRED * sizeof(double);
+    g.lds += (size_t)(g.threads / 64) * sizeof(double);  // reduction scratch
     return g;
   }
 };

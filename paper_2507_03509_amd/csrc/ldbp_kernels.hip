@@ -20,11 +20,12 @@
 // (bitwise the forward's values: the forward rounds to complex64 only at
 // span boundaries), then each step is pulled back in reverse: the Kerr step
 // pointwise from its output z (y = z e^{-i phi}, |y| = |z|), the FIR step as
-// the correlation with conj(h) through an LDS window.  Tap and xi gradients
-// are accumulated per lane over its interior samples, reduced across the
-// wave by recursive halving (32 values in 32 shuffle-adds) and across the
-// workgroup in LDS, and written as per-workgroup partials that a last kernel
-// sums in a fixed order.
+// the correlation with conj(h) through an LDS window.  The tap gradient is
+// a separate phase with its own lane map (wave = group of 5 taps, lane = run
+// of interior samples, sliding 5-sample window), so that its 10 accumulators
+// never share a lane with the pullback's window; each wave reduces its group
+// by recursive halving.  dL/dxi is summed over the workgroup.  Both are
+// written as per-workgroup partials that a last kernel sums in a fixed order.
 #include "kernel_common.hpp"
 #include "ldbp_internal.hpp"
 
@@ -85,9 +86,22 @@ __device__ __forceinline__ void load_taps(const cd* __restrict__ taps15, int k, 
   for (int t = 0; t < TAPS; ++t) h[t] = taps15[k * TAPS + t];
 }
 
-// Window sample d of the lane: a[base - HC + d].
+// The lane owning samples 4 l .. 4 l + 3 (l = threadIdx.x) addresses its
+// window and its own samples from slot 5 l with compile-time offsets (the
+// slot map is affine there), so every LDS access is one base register plus
+// an immediate.
+static_assert(R == 4 && GUARD % 4 == 0, "affine lane addressing needs R = 4");
+__device__ __forceinline__ const cd* lane_base(const cd* a) { return a + 5 * (int)threadIdx.x; }
+__device__ __forceinline__ cd* lane_base(cd* a) { return a + 5 * (int)threadIdx.x; }
+// window sample d (= sample 4 l - HC + d)
+constexpr int win_off(int d) { return (d + GUARD - HC) + ((d + GUARD - HC) >> 2); }
+// own sample r (= sample 4 l + r)
+constexpr int own_off(int r) { return (r + GUARD) + ((r + GUARD) >> 2); }
+
+// Window sample d of the lane: a[base - HC + d] (base = 4 threadIdx.x).
 __device__ __forceinline__ cd window_at(const cd* a, int base, int d) {
-  return a[lslot(base - HC + d)];
+  (void)base;
+  return lane_base(a)[win_off(d)];
 }
 
 // y[r] = sum_t h[t] a[base + r + HC - t]: the FIR step at the lane's samples.
@@ -188,7 +202,7 @@ __global__ __launch_bounds__(512) void ldbp_fwd(FwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) st[p * a.ls + lslot(base + r)] = y[p][r];
+        for (int r = 0; r < R; ++r) lane_base(st + p * a.ls)[own_off(r)] = y[p][r];
     }
     __syncthreads();
     if (a.ckpt && span_end && k + 1 < a.k1) {
@@ -211,15 +225,16 @@ __global__ __launch_bounds__(512) void ldbp_fwd(FwdArgs a, const cd* __restrict_
 // Reductions
 // ---------------------------------------------------------------------------
 
-// Sum v[0..31] over the 64 lanes of the wave by recursive halving: in round
+// Sum v[0..15] over the 64 lanes of the wave by recursive halving: in round
 // r lanes exchange with lane ^ (1 << r) the half of their values they do not
-// keep, so each round halves the values per lane.  Returns, on lane l, the
-// wave sum of value index bitrev5(l & 31) (lanes l and l + 32 agree).
-__device__ __forceinline__ double wave_sum32(double (&v)[NRED]) {
+// keep, so each round halves the values per lane (15 shuffle-adds, then two
+// for the last value).  Returns on lane l the wave sum of value
+// bitrev4(l & 15).
+__device__ __forceinline__ double wave_sum16(double (&v)[16]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int r = 0; r < 5; ++r) {
-    const int half = NRED >> (r + 1);
+  for (int r = 0; r < 4; ++r) {
+    const int half = 16 >> (r + 1);
     const bool upper = (lane >> r) & 1;
 #pragma unroll
     for (int i = 0; i < half; ++i) {
@@ -229,27 +244,72 @@ __device__ __forceinline__ double wave_sum32(double (&v)[NRED]) {
       v[i] = keep + __shfl_xor(send, 1 << r, 64);
     }
   }
-  return v[0] + __shfl_xor(v[0], 32, 64);
+  double x = v[0] + __shfl_xor(v[0], 16, 64);
+  return x + __shfl_xor(x, 32, 64);
 }
 
-__device__ __forceinline__ int bitrev5(int l) {
-  return ((l & 1) << 4) | ((l & 2) << 2) | (l & 4) | ((l & 8) >> 2) | ((l & 16) >> 4);
+__device__ __forceinline__ int bitrev4(int l) {
+  return ((l & 1) << 3) | ((l & 2) << 1) | ((l & 4) >> 1) | ((l & 8) >> 3);
 }
 
-// Sum v over the workgroup into out[0..31] (written by threads 0..31).
-// red: nwaves * 32 doubles of LDS.  Contains barriers.
-__device__ __forceinline__ void block_sum32(double (&v)[NRED], double* red, double* out) {
-  const double s = wave_sum32(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane < 32) red[wave * NRED + bitrev5(lane)] = s;
+// Sum one value over the workgroup into *out (thread 0 writes).  red: at
+// least nwaves doubles of LDS.  Contains barriers.
+__device__ __forceinline__ void block_sum1(double v, double* red, double* out) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x < NRED) {
-    const int nw = (blockDim.x + 63) >> 6;
+  if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += red[w * NRED + threadIdx.x];
-    out[threadIdx.x] = t;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    *out = t;
   }
   __syncthreads();
+}
+
+// Tap gradient of one step over the tile's interior samples n:
+//   dL/dh[t] = sum_{p, n} gy_p[n] conj(x_p[n + c - t]),
+// gy in G and x in X (LDS, both polarisations).  Wave w handles the taps
+// 5 g .. 5 g + 4 of the groups g = w, w + nwaves, ...; its lane l sums a
+// contiguous chunk of samples with a sliding 5-sample window of x (two LDS
+// reads per sample for five complex multiply-adds), and the wave reduces
+// its 10 values and writes them to part[10 g ..] (lanes 0..9).
+template <int P>
+__device__ __forceinline__ void tap_gradient(const cd* G, const cd* X, int ls, int halo, int w,
+                                             double* part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int chunk = (w + 63) >> 6;
+  const int n0 = halo + min(lane * chunk, w), n1 = halo + min(lane * chunk + chunk, w);
+  for (int grp = wave; grp < 3; grp += nw) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = 0.0;
+    const int t0 = 5 * grp;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const cd* Gp = G + p * ls;
+      const cd* Xp = X + p * ls;
+      // xw[u] = x[n + c - t0 - u]
+      cd xw[5];
+#pragma unroll
+      for (int u = 0; u < 5; ++u) xw[u] = Xp[lslot(n0 - 1 + HC - t0 - u)];
+      for (int n = n0; n < n1; ++n) {
+#pragma unroll
+        for (int u = 4; u > 0; --u) xw[u] = xw[u - 1];
+        xw[0] = Xp[lslot(n + HC - t0)];
+        const cd gv = Gp[lslot(n)];
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+          v[2 * u] = fma(gv.re, xw[u].re, fma(gv.im, xw[u].im, v[2 * u]));
+          v[2 * u + 1] = fma(gv.im, xw[u].re, fma(-gv.re, xw[u].im, v[2 * u + 1]));
+        }
+      }
+    }
+    const double sum = wave_sum16(v);
+    const int idx = bitrev4(lane & 15);
+    if (lane < 16 && idx < 10) part[2 * t0 + idx] = sum;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -287,7 +347,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) xs_lds[j * plane + p * a.ls + lslot(base + r)] = y[p][r];
+        for (int r = 0; r < R; ++r) lane_base(xs_lds + j * plane + p * a.ls)[own_off(r)] = y[p][r];
     }
     __syncthreads();
   }
@@ -312,7 +372,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) z[p][r] = xs_lds[(j + 1) * plane + p * a.ls + lslot(base + r)];
+        for (int r = 0; r < R; ++r) z[p][r] = lane_base(xs_lds + (j + 1) * plane + p * a.ls)[own_off(r)];
     }
     // Kerr pullback at the lane's samples (z = output, g = its gradient)
     double xi_part = 0.0;
@@ -342,16 +402,10 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) G[p * a.ls + lslot(base + r)] = gy[p][r];
+        for (int r = 0; r < R; ++r) lane_base(G + p * a.ls)[own_off(r)] = gy[p][r];
     }
     __syncthreads();
-    double acc[NRED];
-#pragma unroll
-    for (int v = 0; v < NRED; ++v) acc[v] = 0.0;
-    // FIR pullback gx[m] = sum_t conj(h[t]) gy[m - c + t], then the tap
-    // gradient dL/dh[t] += gy[m - c + t] conj(x[m]) over the interior samples
-    // m, in two passes over the window so that the 32 accumulators are not
-    // live together with the pullback's outputs and window
+    // FIR pullback at the lane's samples: gx[m] = sum_t conj(h[t]) gy[m - c + t]
     if (active) {
       cd h[TAPS];
       load_taps(taps15, k, h);
@@ -369,36 +423,12 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
             if (t >= 0 && t < TAPS) g[p][r] = cmac(g[p][r], cd{h[t].re, -h[t].im}, v);
           }
         }
-        __builtin_amdgcn_sched_barrier(0);  // one polarisation's window at a time
-      }
-      if (base + R > a.halo && base < a.halo + a.w) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          cd xm[R];
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int i = base + r;
-            xm[r] = (i >= a.halo && i < a.halo + a.w) ? X[p * a.ls + lslot(i)] : cd{0.0, 0.0};
-          }
-#pragma unroll
-          for (int d = 0; d < R + 2 * HC; ++d) {
-            const cd v = window_at(G + p * a.ls, base, d);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const int t = d - r;
-              if (t >= 0 && t < TAPS) {
-                const cd q = cmulc(v, xm[r]);
-                acc[2 * t] += q.re;
-                acc[2 * t + 1] += q.im;
-              }
-            }
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
       }
     }
-    acc[2 * TAPS] = xi_part;
-    block_sum32(acc, red, a.partial + ((int64_t)k * gridDim.x + blockIdx.x) * NRED);
+    double* part = a.partial + ((int64_t)k * gridDim.x + blockIdx.x) * NRED;
+    tap_gradient<P>(G, X, a.ls, a.halo, a.w, part);
+    // dL/dxi: one value, summed over the workgroup
+    block_sum1(xi_part, red, part + 2 * TAPS);
   }
   if (active) {
 #pragma unroll
@@ -421,20 +451,27 @@ __global__ __launch_bounds__(256) void ldbp_pad_taps(const cd* __restrict__ taps
 }
 
 // Parameter gradients: sum the per-workgroup partials of every step in a
-// fixed order.  One workgroup of 256 lanes per step.
-__global__ __launch_bounds__(256) void ldbp_reduce(const double* __restrict__ partial, int blocks,
-                                                   int n_taps, cd* grad_taps, double* grad_xi) {
-  __shared__ double red[8][NRED];
+// fixed order.  One workgroup of 1024 lanes per step: lane (g, v) sums value v
+// of the partials g, g + 32, ... in two interleaved accumulators; the 32
+// groups are then added in order.
+__global__ __launch_bounds__(1024) void ldbp_reduce(const double* __restrict__ partial, int blocks,
+                                                    int n_taps, cd* grad_taps, double* grad_xi) {
+  __shared__ double red[32][NRED + 1];
   const int k = blockIdx.x;
   const int v = threadIdx.x & 31, grp = threadIdx.x >> 5;
-  double s = 0.0;
-  for (int i = grp; i < blocks; i += 8) s += partial[((int64_t)k * blocks + i) * NRED + v];
-  red[grp][v] = s;
+  const double* src = partial + (int64_t)k * blocks * NRED + v;
+  double s0 = 0.0, s1 = 0.0;
+  int i = grp;
+  for (; i + 32 < blocks; i += 64) {
+    s0 += src[(int64_t)i * NRED];
+    s1 += src[(int64_t)(i + 32) * NRED];
+  }
+  if (i < blocks) s0 += src[(int64_t)i * NRED];
+  red[grp][v] = s0 + s1;
   __syncthreads();
   if (threadIdx.x < NRED) {
     double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) t += red[q][v];
+    for (int q = 0; q < 32; ++q) t += red[q][v];
     red[0][v] = t;
   }
   __syncthreads();
@@ -450,7 +487,8 @@ __global__ __launch_bounds__(256) void ldbp_reduce(const double* __restrict__ pa
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void ldbp_loss(LossArgs a) {
   extern __shared__ __align__(16) unsigned char smem_l[];
-  float2* zs = reinterpret_cast<float2*>(smem_l);
+  double* g = reinterpret_cast<double*>(smem_l);            // 2R + 1 taps
+  float2* zs = reinterpret_cast<float2*>(g + 2 * a.mf_half + 2);
   __shared__ double red[4];
   const int64_t row = blockIdx.x / a.tiles;
   const int tile = (int)(blockIdx.x % a.tiles);
@@ -460,17 +498,19 @@ __global__ __launch_bounds__(256) void ldbp_loss(LossArgs a) {
   const int64_t s0 = a.sps * m0 - a.mf_half;
   const int64_t nm = a.n - 1;
   const float2* zr = a.z + row * a.n;
+  for (int i = threadIdx.x; i <= 2 * a.mf_half; i += blockDim.x) g[i] = a.mf[i];
   for (int i = threadIdx.x; i < span; i += blockDim.x) zs[i] = zr[(s0 + i) & nm];
   __syncthreads();
   double part = 0.0;
   if (threadIdx.x < a.ms) {
-    const int c = a.sps * threadIdx.x + a.mf_half;  // local index of sample sps m
+    // u = sum_j g[j + R] z[sps m - j]: local sample index c - j, c = sps t + R
+    const float2* zc = zs + a.sps * threadIdx.x + 2 * a.mf_half;
     cd u{0.0, 0.0};
-    for (int j = -a.mf_half; j <= a.mf_half; ++j) {
-      const float2 v = zs[c - j];
-      const double gj = a.mf[j + a.mf_half];
-      u.re = fma(gj, (double)v.x, u.re);
-      u.im = fma(gj, (double)v.y, u.im);
+#pragma unroll 4
+    for (int q = 0; q <= 2 * a.mf_half; ++q) {   // q = j + R
+      const float2 v = zc[-q];
+      u.re = fma(g[q], (double)v.x, u.re);
+      u.im = fma(g[q], (double)v.y, u.im);
     }
     const int64_t m = m0 + threadIdx.x;
     const float2 sv = a.sym[row * a.m + m];
@@ -503,7 +543,8 @@ __global__ __launch_bounds__(256) void ldbp_loss_total(const double* __restrict_
 // grad[n] = sum_m mf[sps m - n + R] ubar[m] over the symbols within R of n
 __global__ __launch_bounds__(256) void ldbp_mf_adjoint(MfAdjArgs a) {
   extern __shared__ __align__(16) unsigned char smem_m[];
-  cd* us = reinterpret_cast<cd*>(smem_m);
+  double* g = reinterpret_cast<double*>(smem_m);            // 2R + 1 taps
+  cd* us = reinterpret_cast<cd*>(g + 2 * a.mf_half + 2);
   const int64_t row = blockIdx.x / a.tiles;
   const int tile = (int)(blockIdx.x % a.tiles);
   const int64_t nb = (int64_t)tile * a.ns;
@@ -514,21 +555,24 @@ __global__ __launch_bounds__(256) void ldbp_mf_adjoint(MfAdjArgs a) {
   const int cnt = (int)(mhi - mlo + 1);
   const int64_t mm = a.m - 1;
   const cd* ur = a.ubar + row * a.m;
+  for (int i = threadIdx.x; i <= 2 * a.mf_half; i += blockDim.x) g[i] = a.mf[i];
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) us[i] = ur[(mlo + i) & mm];
   __syncthreads();
   for (int q = threadIdx.x; q < a.ns; q += blockDim.x) {
-    const int64_t n = nb + q;
-    const int64_t lo = (n - a.mf_half >= 0) ? (n - a.mf_half + a.sps - 1) / a.sps
-                                            : -((a.mf_half - n) / a.sps);
-    const int64_t hi = (n + a.mf_half) / a.sps;
+    // local coordinates: sample q of the tile is n = nb + q; symbol index
+    // m - mlo = i, tap index sps (i + mlo) - n + R = sps i + off
+    const int off = (int)(a.sps * mlo - nb) - q + a.mf_half;
+    // i with 0 <= sps i + off <= 2R
+    const int lo = off >= 0 ? 0 : (-off + a.sps - 1) / a.sps;
+    const int hi = (2 * a.mf_half - off) / a.sps;
     cd acc{0.0, 0.0};
-    for (int64_t m = lo; m <= hi; ++m) {
-      const double gj = a.mf[a.sps * m - n + a.mf_half];
-      const cd u = us[m - mlo];
+    for (int i = lo; i <= hi; ++i) {
+      const double gj = g[a.sps * i + off];
+      const cd u = us[i];
       acc.re = fma(gj, u.re, acc.re);
       acc.im = fma(gj, u.im, acc.im);
     }
-    store_c64(a.grad + row * a.n + n, acc);
+    store_c64(a.grad + row * a.n + nb + q, acc);
   }
 }
 
@@ -554,7 +598,8 @@ hipError_t launch_bwd(int n_pol, const BwdArgs& a, int threads, size_t lds, hipS
 }
 
 hipError_t launch_loss(const LossArgs& a, int64_t rows, hipStream_t st) {
-  const size_t lds = (size_t)(a.sps * (a.ms - 1) + 2 * a.mf_half + 1) * sizeof(float2);
+  const size_t lds = (size_t)(2 * a.mf_half + 2) * sizeof(double) +
+                     (size_t)(a.sps * (a.ms - 1) + 2 * a.mf_half + 1) * sizeof(float2);
   hipLaunchKernelGGL(ldbp_loss, dim3((unsigned)(rows * a.tiles)), dim3(256), lds, st, a);
   return hipGetLastError();
 }
@@ -566,7 +611,8 @@ hipError_t launch_loss_total(const double* partial, int count, double inv_count,
 }
 
 hipError_t launch_mf_adjoint(const MfAdjArgs& a, int64_t rows, hipStream_t st) {
-  const size_t lds = (size_t)((a.ns + 2 * a.mf_half) / a.sps + 3) * sizeof(cd);
+  const size_t lds = (size_t)(2 * a.mf_half + 2) * sizeof(double) +
+                     (size_t)((a.ns + 2 * a.mf_half) / a.sps + 3) * sizeof(cd);
   hipLaunchKernelGGL(ldbp_mf_adjoint, dim3((unsigned)(rows * a.tiles)), dim3(256), lds, st, a);
   return hipGetLastError();
 }
@@ -580,7 +626,7 @@ hipError_t launch_pad_taps(const cd* taps, int n_steps, int n_taps, cd* taps15, 
 
 hipError_t launch_reduce(const double* partial, int blocks, int n_steps, int n_taps,
                          cd* grad_taps, double* grad_xi, hipStream_t st) {
-  hipLaunchKernelGGL(ldbp_reduce, dim3((unsigned)n_steps), dim3(256), 0, st, partial, blocks,
+  hipLaunchKernelGGL(ldbp_reduce, dim3((unsigned)n_steps), dim3(1024), 0, st, partial, blocks,
                      n_taps, grad_taps, grad_xi);
   return hipGetLastError();
 }
