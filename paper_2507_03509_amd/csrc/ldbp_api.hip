@@ -24,7 +24,7 @@ namespace {
 constexpr int kFwdTile = 1024;
 constexpr int kFwdSteps = 20;
 constexpr int kBwdTile = 512;
-constexpr int kFwdMaxRegion = 512 * L::R;  // forward workgroup <= 512 lanes
+constexpr int kFwdMaxRegion = 512 * L::R;  // forward workgroup <= 1024 lanes (512 per polarisation)
 constexpr int kBwdMaxRegion = 256 * L::R;  // backward workgroup <= 256 lanes
 constexpr int kLossSymbols = 256;          // symbols per loss workgroup
 constexpr int kMfSamples = 512;            // samples per matched-filter-adjoint workgroup
@@ -98,7 +98,11 @@ struct ssfm_ldbp_s {
     return std::max(s, fwd_steps / s * s);
   }
   Geometry fwd_geom(int steps) const {
-    return make_geometry(d.n_samples, fwd_tile, L::HC * steps, 1, d.n_pol, 0);
+    // one polarisation per lane, plus the |y|^2 exchange buffer
+    Geometry g = make_geometry(d.n_samples, fwd_tile, L::HC * steps, 1, d.n_pol, 0);
+    g.threads *= d.n_pol;
+    g.lds += (size_t)d.n_pol * g.region * sizeof(double);
+    return g;
   }
   Geometry bwd_geom() const {
     const int s = d.steps_per_span;

@@ -86,33 +86,32 @@ __device__ __forceinline__ void load_taps(const cd* __restrict__ taps15, int k, 
   for (int t = 0; t < TAPS; ++t) h[t] = taps15[k * TAPS + t];
 }
 
-// The lane owning samples 4 l .. 4 l + 3 (l = threadIdx.x) addresses its
+// The lane owning samples 4 l .. 4 l + 3 addresses its
 // window and its own samples from slot 5 l with compile-time offsets (the
 // slot map is affine there), so every LDS access is one base register plus
 // an immediate.
 static_assert(R == 4 && GUARD % 4 == 0, "affine lane addressing needs R = 4");
-__device__ __forceinline__ const cd* lane_base(const cd* a) { return a + 5 * (int)threadIdx.x; }
-__device__ __forceinline__ cd* lane_base(cd* a) { return a + 5 * (int)threadIdx.x; }
+__device__ __forceinline__ const cd* lane_base(const cd* a, int q) { return a + 5 * q; }
+__device__ __forceinline__ cd* lane_base(cd* a, int q) { return a + 5 * q; }
 // window sample d (= sample 4 l - HC + d)
 constexpr int win_off(int d) { return (d + GUARD - HC) + ((d + GUARD - HC) >> 2); }
 // own sample r (= sample 4 l + r)
 constexpr int own_off(int r) { return (r + GUARD) + ((r + GUARD) >> 2); }
 
-// Window sample d of the lane: a[base - HC + d] (base = 4 threadIdx.x).
-__device__ __forceinline__ cd window_at(const cd* a, int base, int d) {
-  (void)base;
-  return lane_base(a)[win_off(d)];
+// Window sample d of the lane owning samples base = 4 q ..: a[base - HC + d].
+__device__ __forceinline__ cd window_at(const cd* a, int q, int d) {
+  return lane_base(a, q)[win_off(d)];
 }
 
 // y[r] = sum_t h[t] a[base + r + HC - t]: the FIR step at the lane's samples.
 // The window is streamed: each of its R + 14 samples updates the outputs that
 // use it and is dropped, so only the outputs stay live.
-__device__ __forceinline__ void fir_own(const cd* a, int base, const cd (&h)[TAPS], cd (&y)[R]) {
+__device__ __forceinline__ void fir_own(const cd* a, int q, const cd (&h)[TAPS], cd (&y)[R]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) y[r] = cd{0.0, 0.0};
 #pragma unroll
   for (int d = 0; d < R + 2 * HC; ++d) {
-    const cd v = window_at(a, base, d);
+    const cd v = window_at(a, q, d);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int t = r + 2 * HC - d;
@@ -135,16 +134,18 @@ __device__ __forceinline__ void kerr(cd (&y)[P][R], double xi) {
   }
 }
 
-// One forward step at the lane's samples, reading state array st.
+// One forward step at the lane's samples (both polarisations), reading state
+// array st: the forward kernel's arithmetic, bit for bit (the power is the
+// same single add of the two per-polarisation terms).
 template <int P>
-__device__ __forceinline__ void step_own(const cd* st, int ls, int base,
+__device__ __forceinline__ void step_own(const cd* st, int ls, int q,
                                          const cd* __restrict__ taps15, const double* __restrict__ xi,
                                          int k, cd (&y)[P][R]) {
   cd h[TAPS];
   load_taps(taps15, k, h);
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    fir_own(st + p * ls, base, h, y[p]);
+    fir_own(st + p * ls, q, h, y[p]);
     // keep the next polarisation's window loads behind this one's FMAs: the
     // two windows together would not fit the register budget
     __builtin_amdgcn_sched_barrier(0);
@@ -165,12 +166,20 @@ __device__ __forceinline__ void zero_guards(cd* a, int arrays, int ls, int regio
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
+// One polarisation per lane: lanes [p Q, (p + 1) Q) own polarisation p (Q a
+// multiple of 64, so every wave is one polarisation and its window reads
+// stay conflict-free).  The Kerr step couples the polarisations through
+// |y_q|^2, exchanged in LDS; the sum is one add of the two terms
+// (commutative), so both lanes of a sample rotate by the same phase.
 template <int P>
-__global__ __launch_bounds__(512) void ldbp_fwd(FwdArgs a, const cd* __restrict__ taps15,
-                                                 const double* __restrict__ xi) {
+__global__ __launch_bounds__(1024) void ldbp_fwd(FwdArgs a, const cd* __restrict__ taps15,
+                                                  const double* __restrict__ xi) {
   extern __shared__ __align__(16) unsigned char smem_f[];
-  cd* st = reinterpret_cast<cd*>(smem_f);
+  cd* st = reinterpret_cast<cd*>(smem_f);                   // [P][ls]
+  double* pwb = reinterpret_cast<double*>(st + P * a.ls);   // [P][region]
   const int tid = threadIdx.x;
+  const int Q = blockDim.x / P;
+  const int p = tid / Q, q = tid % Q;
   const int64_t b = blockIdx.x / a.tiles;
   const int tile = (int)(blockIdx.x % a.tiles);
   const int64_t n0 = (int64_t)tile * a.w - a.halo;
@@ -179,30 +188,39 @@ __global__ __launch_bounds__(512) void ldbp_fwd(FwdArgs a, const cd* __restrict_
   zero_guards(st, P, a.ls, a.region);
   for (int i = tid; i < a.region; i += blockDim.x) {
 #pragma unroll
-    for (int p = 0; p < P; ++p) st[p * a.ls + lslot(i)] = load_c64(src + p * a.n + ((n0 + i) & nm));
+    for (int pp = 0; pp < P; ++pp)
+      st[pp * a.ls + lslot(i)] = load_c64(src + pp * a.n + ((n0 + i) & nm));
   }
   __syncthreads();
-  const int base = tid * R;
+  const int base = q * R;
   const bool active = base < a.region;
+  cd* mine = st + p * a.ls;
   for (int k = a.k0; k < a.k1; ++k) {
-    cd y[P][R];
-    const bool span_end = (k + 1) % a.spans_steps == 0;
+    cd y[R];
+    double pw[R];
     if (active) {
-      step_own<P>(st, a.ls, base, taps15, xi, k, y);
-      if (span_end) {
-        // the state at a span boundary is the complex64 field
+      cd h[TAPS];
+      load_taps(taps15, k, h);
+      fir_own(mine, q, h, y);
 #pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-          for (int r = 0; r < R; ++r) y[p][r] = round_c64(y[p][r]);
+      for (int r = 0; r < R; ++r) {
+        pw[r] = norm2(y[r]);
+        if constexpr (P == 2) pwb[p * a.region + base + r] = pw[r];
       }
     }
-    __syncthreads();  // every window of this step is read
+    __syncthreads();  // every window of this step is read; |y|^2 published
+    const bool span_end = (k + 1) % a.spans_steps == 0;
     if (active) {
+      const double x = xi[k];
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int r = 0; r < R; ++r) lane_base(st + p * a.ls)[own_off(r)] = y[p][r];
+      for (int r = 0; r < R; ++r) {
+        double tot = pw[r];
+        if constexpr (P == 2) tot = tot + pwb[(1 - p) * a.region + base + r];
+        cd v = cmul(y[r], phasor64(x * tot));
+        // the state at a span boundary is the complex64 field
+        if (span_end) v = round_c64(v);
+        lane_base(mine, q)[own_off(r)] = v;
+      }
     }
     __syncthreads();
     if (a.ckpt && span_end && k + 1 < a.k1) {
@@ -210,14 +228,15 @@ __global__ __launch_bounds__(512) void ldbp_fwd(FwdArgs a, const cd* __restrict_
                    (int64_t)tile * a.w;
       for (int i = tid; i < a.w; i += blockDim.x) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) store_c64(cp + p * a.n + i, st[p * a.ls + lslot(a.halo + i)]);
+        for (int pp = 0; pp < P; ++pp)
+          store_c64(cp + pp * a.n + i, st[pp * a.ls + lslot(a.halo + i)]);
       }
     }
   }
   float2* dst = a.dst + b * P * a.n + (int64_t)tile * a.w;
   for (int i = tid; i < a.w; i += blockDim.x) {
 #pragma unroll
-    for (int p = 0; p < P; ++p) store_c64(dst + p * a.n + i, st[p * a.ls + lslot(a.halo + i)]);
+    for (int pp = 0; pp < P; ++pp) store_c64(dst + pp * a.n + i, st[pp * a.ls + lslot(a.halo + i)]);
   }
 }
 
@@ -343,11 +362,11 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
   for (int j = 1; j < a.s_steps; ++j) {
     cd y[P][R];
     if (active) {
-      step_own<P>(xs_lds + (j - 1) * plane, a.ls, base, taps15, xis, a.k0 + j - 1, y);
+      step_own<P>(xs_lds + (j - 1) * plane, a.ls, tid, taps15, xis, a.k0 + j - 1, y);
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) lane_base(xs_lds + j * plane + p * a.ls)[own_off(r)] = y[p][r];
+        for (int r = 0; r < R; ++r) lane_base(xs_lds + j * plane + p * a.ls, tid)[own_off(r)] = y[p][r];
     }
     __syncthreads();
   }
@@ -372,7 +391,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) z[p][r] = lane_base(xs_lds + (j + 1) * plane + p * a.ls)[own_off(r)];
+        for (int r = 0; r < R; ++r) z[p][r] = lane_base(xs_lds + (j + 1) * plane + p * a.ls, tid)[own_off(r)];
     }
     // Kerr pullback at the lane's samples (z = output, g = its gradient)
     double xi_part = 0.0;
@@ -402,7 +421,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) lane_base(G + p * a.ls)[own_off(r)] = gy[p][r];
+        for (int r = 0; r < R; ++r) lane_base(G + p * a.ls, tid)[own_off(r)] = gy[p][r];
     }
     __syncthreads();
     // FIR pullback at the lane's samples: gx[m] = sum_t conj(h[t]) gy[m - c + t]
@@ -416,7 +435,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
         // window sample d = gy[base - c + d] meets output r through t = d - r
 #pragma unroll
         for (int d = 0; d < R + 2 * HC; ++d) {
-          const cd v = window_at(G + p * a.ls, base, d);
+          const cd v = window_at(G + p * a.ls, tid, d);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const int t = d - r;
