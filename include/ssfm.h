@@ -166,6 +166,32 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
 int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
                const uint64_t* seeds, int hip_device, void* stream);
 
+/* Result of ssfm_plan_autotune. */
+typedef struct ssfm_tune_info {
+  int32_t columns;        /* chosen column-tile width (0: nothing to tune)    */
+  int32_t row_lanes;      /* chosen row-pass workgroup size (0: likewise)     */
+  int32_t candidates;     /* timed variants: entries of us_per_step           */
+  int32_t reserved;
+  double us_per_step[4];  /* one split step per variant, in the order
+                             (narrow columns, narrow rows), (narrow, wide),
+                             (wide, narrow), (wide, wide); microseconds       */
+} ssfm_tune_info;
+
+/* Choose the launch shape of the four-step path for `batch` realisations by
+ * measurement: each combination of column tile (narrow: 2 columns; wide: 8,
+ * or 4 at N1 = 512) and row workgroup (narrow: 64 lanes; wide: 256) runs a
+ * few split steps (row pass + nonlinear column pass) on a scratch field on
+ * `stream`, timed with HIP events, and the fastest is recorded in the plan
+ * for this batch size.  Later forward calls with this batch use it (the
+ * SSFM_COLUMNS environment override still takes precedence).  The variants
+ * compute every transform with the same FP64 arithmetic, so results do not
+ * depend on the choice, bit for bit.  Synchronises `stream`; allocates and
+ * frees a batch-sized scratch field; not to be called while another call on
+ * the plan runs.  On the LDS-resident path (n_samples <= 8192) there is
+ * nothing to tune: *info reports zeros.  Errors: SSFM_EINVAL (NULL plan or
+ * info, batch < 1), SSFM_ENOMEM, SSFM_EHIP. */
+int ssfm_plan_autotune(ssfm_plan_t plan, int64_t batch, void* stream, ssfm_tune_info* info);
+
 /* Per-kernel timing, for reporting achieved bandwidth.  Between
  * ssfm_profile_begin and ssfm_profile_end every kernel launch of this plan
  * is bracketed by two HIP events recorded on the launch's own stream; the

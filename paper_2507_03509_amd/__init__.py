@@ -23,6 +23,7 @@ __all__ = [
     "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch",
     "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
     "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats", "propagate",
+    "SsfmTuneInfo", "ssfm_plan_autotune",
     "SSFM_OK", "SSFM_EINVAL", "SSFM_ENOMEM", "SSFM_EHIP", "SSFM_EUNSUPPORTED",
 ]
 
@@ -89,6 +90,22 @@ class SsfmKernelStats(ctypes.Structure):
     ]
 
 
+class SsfmTuneInfo(ctypes.Structure):
+    """Mirror of ``ssfm_tune_info``."""
+
+    _fields_ = [
+        ("columns", ctypes.c_int32),
+        ("row_lanes", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("us_per_step", ctypes.c_double * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"columns": self.columns, "row_lanes": self.row_lanes,
+                "us_per_step": list(self.us_per_step)[: self.candidates]}
+
+
 class SsfmError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         self.status = status
@@ -119,6 +136,7 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_adjoint.argtypes = [P, VP, VP, I64, U64, VP]
     lib.ssfm_batch.argtypes = [ctypes.POINTER(SsfmLink), ctypes.POINTER(ctypes.c_void_p), I64,
                                ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, VP]
+    lib.ssfm_plan_autotune.argtypes = [P, I64, VP, ctypes.POINTER(SsfmTuneInfo)]
     lib.ssfm_profile_begin.argtypes = [P]
     lib.ssfm_profile_end.argtypes = [P, ctypes.POINTER(SsfmKernelStats), ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_int)]
@@ -129,7 +147,7 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_version.argtypes = []
     for name in ("ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info", "ssfm_forward",
                  "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version",
-                 "ssfm_profile_begin", "ssfm_profile_end"):
+                 "ssfm_profile_begin", "ssfm_profile_end", "ssfm_plan_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -270,6 +288,22 @@ def ssfm_adjoint(plan: int, field_in, grad, seed: int = 0, stream=None) -> None:
                                        _stream_ptr(field_in, stream)), "ssfm_adjoint")
 
 
+def ssfm_plan_autotune(plan: int, batch: int, stream=None) -> dict:
+    """Measure the four-step launch shapes for ``batch`` and record the
+    fastest in the plan (see include/ssfm.h)."""
+    info = SsfmTuneInfo()
+    st = None
+    if stream is not None:
+        st = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    else:
+        import torch
+        if torch.cuda.is_available():
+            st = torch.cuda.current_stream().cuda_stream
+    _check(load_library().ssfm_plan_autotune(plan, int(batch), st, ctypes.byref(info)),
+           "ssfm_plan_autotune")
+    return info.as_dict()
+
+
 def ssfm_batch(links, fields, seeds, hip_device: int = 0, stream=None) -> None:
     n = len(links)
     arr = (SsfmLink * n)(*[l if isinstance(l, SsfmLink) else make_link(l) for l in links])
@@ -304,6 +338,10 @@ class Plan:
         ssfm_forward_spans(self.handle, field, seed, realization0, span_begin, span_end,
                            stream)
         return field
+
+    def autotune(self, batch: int, stream=None) -> dict:
+        """Choose this plan's launch shape for ``batch`` by measurement."""
+        return ssfm_plan_autotune(self.handle, batch, stream)
 
     def adjoint(self, field_in, grad, seed: int = 0, stream=None):
         """In-place on ``grad``: dL/dA_out* -> dL/dA_in* (see ssfm_adjoint)."""

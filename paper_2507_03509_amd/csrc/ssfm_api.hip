@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -96,6 +97,12 @@ struct ssfm_plan_s {
              s0 == o.s0 && s1 == o.s1 && stream == o.stream;
     }
   };
+  // launch shapes chosen by ssfm_plan_autotune, per batch size
+  struct Shape {
+    bool wide_cols = false, wide_rows = false;
+  };
+  std::mutex tune_mu;
+  std::map<int64_t, Shape> tuned;
   std::mutex graph_mu;
   GraphKey last_key;
   bool have_last = false;
@@ -288,18 +295,36 @@ int64_t launches_per_call(const ssfm_plan_s* p) {
 // Column tiles: wide once a batch offers at least two workgroups per compute
 // unit, otherwise narrow.  SSFM_COLUMNS (a tile width among the compiled
 // ones) overrides the choice, for tuning.
-const ssfm::FourStepKernels& pick_cols(const ssfm_plan_s* p, int64_t batch, bool* wide) {
+// Launch shape of a four-step call: SSFM_COLUMNS override, else the shape
+// ssfm_plan_autotune recorded for this batch, else wide tiles once the batch
+// gives at least 512 column workgroups.
+struct Shape4 {
+  const ssfm::FourStepKernels* cols;
+  ssfm::RowLaunch row;
+  bool wide_cols, wide_rows;
+};
+
+Shape4 pick_shape(ssfm_plan_s* p, int64_t batch) {
   const char* env = getenv("SSFM_COLUMNS");
   if (env) {
     const int c = atoi(env);
     for (const ssfm::FourStepKernels* k : {&p->ks.wide, &p->ks.mid, &p->ks.narrow})
       if (k->columns == c) {
-        *wide = k != &p->ks.narrow;
-        return *k;
+        const bool w = k != &p->ks.narrow;
+        return {k, w ? p->ks.row_wide : p->ks.row_narrow, w, w};
       }
   }
-  *wide = batch * (p->ks.n2 / p->ks.wide.columns) >= 512;
-  return *wide ? p->ks.wide : p->ks.narrow;
+  {
+    std::lock_guard<std::mutex> lock(p->tune_mu);
+    auto it = p->tuned.find(batch);
+    if (it != p->tuned.end()) {
+      const auto& t = it->second;
+      return {t.wide_cols ? &p->ks.wide : &p->ks.narrow,
+              t.wide_rows ? p->ks.row_wide : p->ks.row_narrow, t.wide_cols, t.wide_rows};
+    }
+  }
+  const bool w = batch * (p->ks.n2 / p->ks.wide.columns) >= 512;
+  return {w ? &p->ks.wide : &p->ks.narrow, w ? p->ks.row_wide : p->ks.row_narrow, w, w};
 }
 
 // Graph replay for the four-step path (many launches per call); not while a
@@ -337,9 +362,9 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
       return api_fail_hip(e, "k1_lds launch");
     return SSFM_OK;
   }
-  bool wide = false;
-  const ssfm::FourStepKernels& cols = pick_cols(p, batch, &wide);
-  const ssfm::RowLaunch row = wide ? ks.row_wide : ks.row_narrow;
+  const Shape4 shape = pick_shape(p, batch);
+  const ssfm::FourStepKernels& cols = *shape.cols;
+  const ssfm::RowLaunch row = shape.row;
   const int64_t rows = batch * p->n_pol * ks.n1;
   int log2_n2 = 0;
   while ((1 << log2_n2) < ks.n2) ++log2_n2;
@@ -628,9 +653,7 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
 
   // reverse sweep: state and cotangent together, span by span
   const int64_t batch2 = 2 * batch;
-  bool wide = false;
-  (void)pick_cols(plan, batch2, &wide);
-  const ssfm::RowLaunch row = wide ? ks.row_wide : ks.row_narrow;
+  const ssfm::RowLaunch row = pick_shape(plan, batch2).row;
   const int64_t rows = batch2 * plan->n_pol * ks.n1;
   const double row_bytes = 2.0 * (double)batch2 * plan->n_pol * (double)plan->n * sizeof(float2);
   int log2_n2 = 0;
@@ -763,6 +786,98 @@ int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
     if (rc != SSFM_OK) return rc;
     if (e != hipSuccess) return api_fail_hip(e, "ssfm_batch copies");
   }
+  return SSFM_OK;
+}
+
+int ssfm_plan_autotune(ssfm_plan_t plan, int64_t batch, void* stream, ssfm_tune_info* info) {
+  ssfm::api_clear_error();
+  if (!plan || !info) return api_fail(SSFM_EINVAL, "NULL plan or info");
+  if (batch < 1) return api_fail(SSFM_EINVAL, "batch must be >= 1 (got %lld)", (long long)batch);
+  *info = ssfm_tune_info{};
+  const ssfm::KernelSet& ks = plan->ks;
+  if (ks.path != 2) return SSFM_OK;
+  DeviceGuard guard(plan->device);
+  if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t bytes = (size_t)batch * plan->n_pol * plan->n * sizeof(float2);
+  float2* f = nullptr;
+  if (hipMalloc(&f, bytes) != hipSuccess)
+    return api_fail(SSFM_ENOMEM, "autotune scratch field of %zu bytes", bytes);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMemsetAsync(f, 0, bytes, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int log2_n2 = 0;
+  while ((1 << log2_n2) < ks.n2) ++log2_n2;
+  ssfm::RowArgs ra{};
+  ra.field = f;
+  ra.H = plan->h_full;
+  ra.tw = plan->tw2;
+  ra.twA = plan->twA;
+  ra.twB = plan->twB;
+  ra.n1 = ks.n1;
+  ra.log2_n2 = log2_n2;
+  ssfm::ColArgs a{};
+  a.field = f;
+  a.tw1 = plan->tw1;
+  a.n2 = ks.n2;
+  a.n = plan->n;
+  a.kappa = plan->kappa.empty() ? 0.0 : plan->kappa[0];
+  const int64_t rows = batch * plan->n_pol * ks.n1;
+  double best = 0.0;
+  int best_idx = -1;
+  for (int idx = 0; idx < 4 && e == hipSuccess; ++idx) {
+    const ssfm::FourStepKernels& cols = (idx >> 1) ? ks.wide : ks.narrow;
+    const ssfm::RowLaunch row = (idx & 1) ? ks.row_wide : ks.row_narrow;
+    // one split step: row pass, nonlinear column pass
+    auto step = [&]() -> hipError_t {
+      hipError_t r = row(ra, rows, st);
+      return r == hipSuccess ? cols.col[ssfm::MODE_NL](a, batch, st) : r;
+    };
+    if ((e = step()) != hipSuccess) break;  // warm-up
+    int reps = 3;
+    float ms = 0.0f;
+    for (int round = 0; round < 2 && e == hipSuccess; ++round) {
+      if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = step();
+      if (e != hipSuccess || (e = hipEventRecord(e1, st)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      // at least ~2 ms of work in the measured round
+      if (ms >= 2.0f) break;
+      reps = (int)std::min<double>(1000.0, std::ceil(reps * 2.0 / std::max(ms, 1e-3f)));
+    }
+    if (e != hipSuccess) break;
+    info->us_per_step[idx] = 1e3 * (double)ms / reps;
+    if (best_idx < 0 || info->us_per_step[idx] < best) {
+      best = info->us_per_step[idx];
+      best_idx = idx;
+    }
+  }
+  const hipError_t es = hipStreamSynchronize(st);
+  (void)hipFree(f);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return api_fail_hip(e, "autotune");
+  if (es != hipSuccess) return api_fail_hip(es, "autotune synchronise");
+  ssfm_plan_s::Shape sh;
+  sh.wide_cols = (best_idx >> 1) != 0;
+  sh.wide_rows = (best_idx & 1) != 0;
+  {
+    std::lock_guard<std::mutex> lock(plan->tune_mu);
+    plan->tuned[batch] = sh;
+  }
+  {
+    // the replay graph may hold the previous shape
+    std::lock_guard<std::mutex> lock(plan->graph_mu);
+    plan->have_last = false;
+    plan->graph_valid = false;
+    if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+    plan->graph_exec = nullptr;
+  }
+  info->columns = sh.wide_cols ? ks.wide.columns : ks.narrow.columns;
+  info->row_lanes = sh.wide_rows ? ks.rows_wide * (ks.n2 / 16) : ks.rows_narrow * (ks.n2 / 16);
+  info->candidates = 4;
   return SSFM_OK;
 }
 

@@ -45,6 +45,16 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(ssfm.SsfmPlanInfo) == 32
 
 
+def test_tune_info_layout_and_null_arguments():
+    import ctypes
+    assert ctypes.sizeof(ssfm.SsfmTuneInfo) == 48
+    assert ssfm.SsfmTuneInfo.us_per_step.offset == 16
+    lib = ssfm.load_library()
+    info = ssfm.SsfmTuneInfo()
+    assert lib.ssfm_plan_autotune(None, 4, None, ctypes.byref(info)) == ssfm.SSFM_EINVAL
+    assert ssfm.ssfm_last_error()
+
+
 def test_status_strings_and_version():
     assert ssfm.ssfm_status_string(0) == "success"
     assert ssfm.ssfm_status_string(-1) == "invalid argument"
