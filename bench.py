@@ -101,6 +101,35 @@ def traffic_record(kernel: str):
     return ent
 
 
+def _oracle_realisation(task):
+    """CPU-baseline worker (all-cores leg): one oracle propagation of a
+    workload realisation; returns its wall seconds."""
+    import numpy as np
+
+    import oracle
+    from workloads import CONFIGS, make_field
+    wid, r = task
+    w = CONFIGS[wid]
+    a = make_field(w, seed=w.symbol_seed + r)
+    t0 = time.perf_counter()
+    oracle.propagate(a, w.link, seed=w.ase_seed, realization=r)
+    return time.perf_counter() - t0
+
+
+def cpu_all_cores(workload: int, budget_s: float):
+    """The oracle on every host core (a spawned process per core, one
+    realisation each, started before this process touches the GPU): returns
+    (realisations, wall seconds, workers)."""
+    import concurrent.futures
+    import multiprocessing
+    workers = max(1, min(16, os.cpu_count() or 1))
+    ctx = multiprocessing.get_context("spawn")
+    t0 = time.perf_counter()
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        list(ex.map(_oracle_realisation, [(workload, r) for r in range(workers)]))
+    return workers, time.perf_counter() - t0, workers
+
+
 def bench_mixed_batch(args) -> int:
     """Workload 4: 256 independent dual-pol realisations with lengths drawn
     from 2^12..2^16, launch power in [-4, +6] dBm, 1..10 spans of 50 steps and
@@ -309,6 +338,14 @@ def main() -> int:
               "path has no multi-GPU code", file=sys.stderr)
         return 2
 
+    # all-cores oracle leg first: its worker processes are spawned before this
+    # process initialises the GPU
+    cpu_all = None
+    if not args.no_cpu_baseline:
+        done_all, sec_all, workers = cpu_all_cores(args.workload, args.cpu_seconds)
+        cpu_all = (done_all, sec_all, workers)
+        log(f"oracle on {workers} cores: {done_all} realisation(s) in {sec_all:.1f} s")
+
     import numpy as np
     import torch
 
@@ -443,6 +480,45 @@ def main() -> int:
                   "sample_steps_per_s": n * total_steps / (ms1 / 1e3)}
         log(f"batch 1: {ms1:.3f} ms/call, {single['sample_steps_per_s']:.4e} sample-steps/s")
 
+    # ---- batch 64: 64 MiB of field, resident in the 256 MB last-level cache --
+    b64 = None
+    if args.single_steps > 0 and batch >= 64:
+        f64 = field[:64].clone()
+        plan.forward(f64, seed=w.ase_seed, stream=stream)
+        plan.forward(f64, seed=w.ase_seed, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.single_steps):
+            plan.forward(f64, seed=w.ase_seed, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = e0.elapsed_time(e1) / args.single_steps
+        b64 = {"ms_per_call": round(ms64, 3),
+               "us_per_split_step": round(ms64 * 1e3 / total_steps, 3),
+               "sample_steps_per_s": 64 * n * total_steps / (ms64 / 1e3)}
+        log(f"batch 64: {ms64:.3f} ms/call, {b64['sample_steps_per_s']:.4e} sample-steps/s")
+        del f64
+
+    # ---- achievable bandwidth: this library's plain copy kernel on the
+    # batch field (read + write of 2^29 bytes) -------------------------------
+    dst = torch.empty_like(field)
+    ssfm.ssfm_stream_copy(dst, field, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        ssfm.ssfm_stream_copy(dst, field, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * field.numel() * 8 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    roofline["copy_kernel_gbs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log(f"copy kernel: {copy_gbs:.1f} GB/s (the column pass reaches {achieved / copy_gbs:.2f} of it)")
+    del dst
+
     # ---- CPU oracle on one realisation (also the parity reference) ----------
     cpu = None
     rel_err = None
@@ -480,9 +556,16 @@ def main() -> int:
         "rel_err_vs_oracle": rel_err,
         "fwd_adjoint_ms": adj["fwd_adjoint_ms"] if adj else None,
         "fwd_adjoint_ratio": adj["ratio_to_forward"] if adj else None,
+        "pol_sample_steps_per_s": value * p,
         "batch1": single,
+        "batch64": b64,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": None if cpu_all is None else {
+            "value": cpu_all[0] * n * total_steps / cpu_all[1], "unit": "sample-steps/s",
+            "cores": cpu_all[2], "kind": "oracle",
+            "sample": f"{cpu_all[0]} realisation(s), one per spawned process, in "
+                      f"{cpu_all[1]:.1f} s wall"},
     }
     print(json.dumps(out), flush=True)
     plan.close()

@@ -212,6 +212,14 @@ int ssfm_profile_begin(ssfm_plan_t plan);
  * number written.  SSFM_EINVAL on NULL arguments, SSFM_EHIP on event errors. */
 int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int* count);
 
+/* Measurement utility (not part of the propagation): copy `bytes` (a
+ * multiple of 16) from device buffer src to dst on `stream` with a plain
+ * 16-byte-per-lane grid-stride kernel -- the achievable HBM bandwidth the
+ * propagation kernels are compared with.  Asynchronous.  SSFM_EINVAL for
+ * NULL or 16-byte-misaligned pointers or a size not a multiple of 16,
+ * SSFM_EHIP on a launch failure. */
+int ssfm_stream_copy(void* dst, const void* src, int64_t bytes, void* stream);
+
 /* Static description of a status code (never NULL). */
 const char* ssfm_status_string(int status);
 

@@ -23,7 +23,7 @@ __all__ = [
     "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch",
     "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
     "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats", "propagate",
-    "SsfmTuneInfo", "ssfm_plan_autotune",
+    "SsfmTuneInfo", "ssfm_plan_autotune", "ssfm_stream_copy",
     "SSFM_OK", "SSFM_EINVAL", "SSFM_ENOMEM", "SSFM_EHIP", "SSFM_EUNSUPPORTED",
 ]
 
@@ -137,6 +137,7 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_batch.argtypes = [ctypes.POINTER(SsfmLink), ctypes.POINTER(ctypes.c_void_p), I64,
                                ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, VP]
     lib.ssfm_plan_autotune.argtypes = [P, I64, VP, ctypes.POINTER(SsfmTuneInfo)]
+    lib.ssfm_stream_copy.argtypes = [VP, VP, I64, VP]
     lib.ssfm_profile_begin.argtypes = [P]
     lib.ssfm_profile_end.argtypes = [P, ctypes.POINTER(SsfmKernelStats), ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_int)]
@@ -147,7 +148,8 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_version.argtypes = []
     for name in ("ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info", "ssfm_forward",
                  "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version",
-                 "ssfm_profile_begin", "ssfm_profile_end", "ssfm_plan_autotune"):
+                 "ssfm_profile_begin", "ssfm_profile_end", "ssfm_plan_autotune",
+                 "ssfm_stream_copy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -302,6 +304,16 @@ def ssfm_plan_autotune(plan: int, batch: int, stream=None) -> dict:
     _check(load_library().ssfm_plan_autotune(plan, int(batch), st, ctypes.byref(info)),
            "ssfm_plan_autotune")
     return info.as_dict()
+
+
+def ssfm_stream_copy(dst, src, stream=None) -> None:
+    """Copy the device tensor ``src`` into ``dst`` (same byte size) with the
+    library's plain copy kernel (the bandwidth reference)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src differ in size")
+    _check(load_library().ssfm_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes,
+                                           _stream_ptr(src, stream)), "ssfm_stream_copy")
 
 
 def ssfm_batch(links, fields, seeds, hip_device: int = 0, stream=None) -> None:
