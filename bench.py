@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--single-steps", type=int, default=3,
                     help="timed calls of the batch-1 figure (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default launch-shape heuristic instead of measuring")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample")
     ap.add_argument("--adjoint", type=int, default=1,
@@ -385,6 +387,15 @@ def main() -> int:
     info = plan.info
     stream = torch.cuda.current_stream(dev)
     log(f"workload {w.name} batch={batch} plan={info}")
+    # launch shapes by measurement for every batch size timed below (untimed;
+    # the shapes do not change results)
+    tuned = {}
+    if not args.no_autotune:
+        for bsz in sorted({batch, 64, 1}):
+            if bsz <= batch:
+                tuned[bsz] = plan.autotune(bsz, stream)
+                log(f"autotune batch {bsz}: columns {tuned[bsz]['columns']}, row workgroup "
+                    f"{tuned[bsz]['row_lanes']} lanes, us/step {tuned[bsz]['us_per_step']}")
 
     # ---- first call doubles as the parity sample (realisation 0) ------------
     plan.forward(field, seed=w.ase_seed, stream=stream)
@@ -559,6 +570,8 @@ def main() -> int:
         "pol_sample_steps_per_s": value * p,
         "batch1": single,
         "batch64": b64,
+        "launch_shapes": {str(k): {"columns": v["columns"], "row_lanes": v["row_lanes"]}
+                          for k, v in tuned.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": None if cpu_all is None else {

@@ -804,7 +804,9 @@ int ssfm_plan_autotune(ssfm_plan_t plan, int64_t batch, void* stream, ssfm_tune_
   if (hipMalloc(&f, bytes) != hipSuccess)
     return api_fail(SSFM_ENOMEM, "autotune scratch field of %zu bytes", bytes);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipMemsetAsync(f, 0, bytes, st);
+  // a nonzero field (0.01 + 0.01i everywhere): the kernels run measurably
+  // faster on an all-zero one
+  hipError_t e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(f), 0x3c23d70au, bytes / 4, st);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   int log2_n2 = 0;
