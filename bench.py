@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--single-steps", type=int, default=3,
                     help="timed calls of the batch-1 figure (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ldbp-checkpoint-steps", type=int, default=0,
+                    help="workload 5: steps between checkpoints (default: the span, "
+                         "2 steps); 1 = every step, no recompute in the backward")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default launch-shape heuristic instead of measuring")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -239,7 +242,8 @@ def bench_ldbp(args) -> int:
     taps_h, xi_h = ldbp.init_params(ln, cfg.n_taps, cfg.steps_per_span)
     taps = torch.from_numpy(taps_h).to(dev)
     xi = torch.from_numpy(xi_h).to(dev)
-    model = ldbp.Ldbp(n_pol=P, n_steps=K, n_taps=cfg.n_taps, steps_per_span=cfg.steps_per_span,
+    ck_steps = args.ldbp_checkpoint_steps or cfg.steps_per_span
+    model = ldbp.Ldbp(n_pol=P, n_steps=K, n_taps=cfg.n_taps, steps_per_span=ck_steps,
                       n_samples=N, sps=w.sps, mf_taps=2 * cfg.mf_half + 1, device=0)
     ck = model.new_checkpoints(B)
     stream = torch.cuda.current_stream(dev)
@@ -314,6 +318,7 @@ def bench_ldbp(args) -> int:
                                f"{ln.n_spans} x {ln.span_km:g} km, {cfg.steps_per_span} "
                                f"steps/span, {cfg.n_taps} taps, MSE through a "
                                f"{2 * cfg.mf_half + 1}-tap RRC matched filter",
+                   "checkpoint_every_steps": ck_steps,
                    "sample_steps_per_pass": work, "parallelism": "single-gpu"},
         "ms_forward_and_loss": round(ms_fwd, 4), "ms_train_step": round(ms_train, 4),
         "fwd_adjoint_over_fwd": round(ms_train / ms_fwd, 3),
