@@ -239,3 +239,59 @@ def test_autograd_training_step(ldbp):
     assert rel(xd.grad.cpu().numpy(), wx) < GRAD_TOL
     assert rel(td.grad.cpu().numpy(), wt) < GRAD_TOL
     assert rel(xid.grad.cpu().numpy(), wxi) < GRAD_TOL
+
+
+def test_invalid_calls_are_rejected(ldbp):
+    import paper_2507_03509_amd as ssfm
+    b, p, n, k, s, t = 1, 2, 1024, 4, 2, 15
+    _, x, taps, xi = problem(7, b, p, n, k, t)
+    model = make_model(ldbp, b, p, n, k, s, t)
+    xd, td, xid = dev(x, torch.complex64), dev(taps, torch.complex128), dev(xi, torch.float64)
+    out = torch.empty_like(xd)
+    ck = model.new_checkpoints(b)
+    lib = ssfm.load_library()
+    h = model.handle
+    # in place, misaligned field, NULL taps
+    assert lib.ssfm_ldbp_forward(h, xd.data_ptr(), xd.data_ptr(), td.data_ptr(), xid.data_ptr(),
+                                 b, None, None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_ldbp_forward(h, xd.data_ptr() + 4, out.data_ptr(), td.data_ptr(),
+                                 xid.data_ptr(), b, None, None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_ldbp_forward(h, xd.data_ptr(), out.data_ptr(), None, xid.data_ptr(), b, None,
+                                 None) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_ldbp_forward(h, xd.data_ptr(), out.data_ptr(), td.data_ptr(), xid.data_ptr(),
+                                 0, None, None) == ssfm.SSFM_EINVAL
+    # the backward needs the checkpoints when there is more than one span
+    z = model.forward(xd, td, xid, ck)
+    g = torch.ones_like(z)
+    gt = torch.empty_like(td)
+    gx = torch.empty_like(xid)
+    assert lib.ssfm_ldbp_backward(h, xd.data_ptr(), z.data_ptr(), td.data_ptr(), xid.data_ptr(), b,
+                                  None, g.data_ptr(), gt.data_ptr(), gx.data_ptr(),
+                                  None) == ssfm.SSFM_EINVAL
+    assert "checkpoints" in ssfm.ssfm_last_error()
+    # the loss without its gradient
+    sym = dev(np.zeros((b, p, n // 2)), torch.complex64)
+    mf = dev(rrc_taps(2, 0.1, 8), torch.float64)
+    loss, gnone = model.loss(z, sym, mf, want_grad=False)
+    torch.cuda.synchronize()
+    assert gnone is None and float(loss.item()) > 0
+
+
+def test_large_field_single_realisation(ldbp):
+    # 2^20 samples per polarisation: 1024 forward tiles, 2048 backward tiles
+    b, p, n, k, s, t = 1, 2, 1 << 20, 4, 2, 15
+    print("ldbp large field", flush=True)
+    rng, x, taps, xi = problem(8, b, p, n, k, t)
+    gz = c64((rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)) / np.sqrt(2))
+    model = make_model(ldbp, b, p, n, k, s, t)
+    xd, td, xid = dev(x, torch.complex64), dev(taps, torch.complex128), dev(xi, torch.float64)
+    ck = model.new_checkpoints(b)
+    z = model.forward(xd, td, xid, ck)
+    g, gt, gxi = model.backward(xd, z, td, xid, ck, dev(gz, torch.complex64))
+    torch.cuda.synchronize()
+    x64 = x.astype(np.complex128)
+    assert rel(z.cpu().numpy(), oracle.ldbp_forward(x64, taps, xi)) < FWD_TOL
+    wx, wt, wxi = oracle.ldbp_backward(x64, taps, xi, gz.astype(np.complex128))
+    assert rel(g.cpu().numpy(), wx) < GRAD_TOL
+    assert rel(gt.cpu().numpy(), wt) < GRAD_TOL
+    assert rel(gxi.cpu().numpy(), wxi) < GRAD_TOL
