@@ -226,6 +226,47 @@ __device__ __forceinline__ int lds_slot(int i, int ls) {
   return PAD == 1 ? i + (i >> 4) : PAD == 2 ? (i + (i >> 4)) * ls : i * ls;
 }
 
+// The pass twiddles a lane uses, read once: entry 1 of row jj mod ns(p) for
+// each butterfly jj = j + T q (q < 16/R) of every pass p >= 1.  A kernel that
+// runs many transforms keeps them in registers instead of reading the table
+// inside every transform (where the read would wait behind the lane's other
+// outstanding global loads).
+template <int M>
+struct fft_twiddles {
+  using S = fft_shape<M>;
+  static constexpr int first(int P) {
+    int c = 0;
+    for (int p = 1; p < P; ++p) c += 16 / S::radix(p);
+    return c;
+  }
+  static constexpr int count = first(S::passes);
+  cd w[count > 0 ? count : 1];
+
+  __device__ __forceinline__ void load(const cd* __restrict__ tw, int j) {
+#pragma unroll
+    for (int p = 1; p < S::passes; ++p) {
+      const int R = S::radix(p), NS = S::ns(p);
+#pragma unroll
+      for (int q = 0; q < 16 / R; ++q)
+        w[first(p) + q] = tw[S::tw_offset(p) + ((j + S::T * q) % NS) * R + 1];
+    }
+  }
+};
+
+// W_{NS R}^k of butterfly jj (= j + T q) in pass P, from the table or from
+// the lane's preloaded set.  (Every level takes the twiddle source as a
+// restrict pointer: without it the compiler serialises the row pass's field
+// loads.)
+template <int M, int P>
+__device__ __forceinline__ cd pass_twiddle(const cd* __restrict__ tw, int jj, int) {
+  using S = fft_shape<M>;
+  return tw[S::tw_offset(P) + (jj % S::ns(P)) * S::radix(P) + 1];
+}
+template <int M, int P>
+__device__ __forceinline__ cd pass_twiddle(const fft_twiddles<M>* __restrict__ tw, int, int q) {
+  return tw->w[fft_twiddles<M>::first(P) + q];
+}
+
 // Read the inputs of pass P from LDS into the registers.
 template <int M, int P, int PAD, typename L>
 __device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, int j) {
@@ -243,9 +284,9 @@ __device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, i
 
 // Twiddle, butterfly and write of pass P.  DST_REG: the outputs stay in the
 // registers (last pass), otherwise they are written to LDS.
-template <int M, int P, bool INV, bool DST_REG, int PAD, typename L>
+template <int M, int P, bool INV, bool DST_REG, int PAD, typename L, typename TW>
 __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int j,
-                                             const cd* __restrict__ tw) {
+                                             TW __restrict__ tw) {
   using S = fft_shape<M>;
   constexpr int R = S::radix(P);
   constexpr int NS = S::ns(P);
@@ -262,8 +303,7 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
       // block (row k, entry 1), powers by FP64 products (~r ulps of FP64, far
       // below the single-precision storage of the field; one load per
       // butterfly keeps the register footprint down)
-      const cd* t = tw + S::tw_offset(P) + (jj % NS) * R;
-      const cd w = t[1];
+      const cd w = pass_twiddle<M, P>(tw, jj, q);
       cd wr = w;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
@@ -283,9 +323,9 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
   }
 }
 
-template <int M, bool INV, int P, int NT, int PAD, bool WAVE, typename L>
+template <int M, bool INV, int P, int NT, int PAD, bool WAVE, typename L, typename TW>
 __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride, int ls,
-                                         int j, const cd* __restrict__ tw) {
+                                         int j, TW __restrict__ tw) {
   using S = fft_shape<M>;
   if constexpr (P < S::passes) {
     constexpr bool last = P == S::passes - 1;
@@ -300,18 +340,9 @@ __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride,
   }
 }
 
-// NT unnormalised transforms of length M advanced in lockstep (they share the
-// barriers); transform t uses the LDS region starting at lds + t * tstride.
-// Lane j holds elements j + (M/16) r of each transform on entry and on exit.
-// Forward uses exp(-2 pi i nk/M), inverse exp(+2 pi i nk/M).
-// Contains barriers (see fft_multi).
-// PAD selects the slot map (lds_slot); a padded transform occupies M + M/16
-// slots (rows of ls slots for PAD = 2).  WAVE: every lane sharing the LDS
-// regions is in the calling wave (see xsync); otherwise the whole block must
-// call.
-template <int M, bool INV, int NT, int PAD, bool WAVE, typename L>
-__device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride, int ls,
-                                          int j, const cd* __restrict__ tw) {
+template <int M, bool INV, int NT, int PAD, bool WAVE, typename L, typename TW>
+__device__ __forceinline__ void fft_multi_impl(cd (&reg)[NT][16], L* lds, int tstride, int ls,
+                                               int j, TW __restrict__ tw) {
   using S = fft_shape<M>;
   if constexpr (S::passes == 1) {
 #pragma unroll
@@ -325,10 +356,32 @@ __device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride
   }
 }
 
+// NT unnormalised transforms of length M advanced in lockstep (they share the
+// barriers); transform t uses the LDS region starting at lds + t * tstride.
+// Lane j holds elements j + (M/16) r of each transform on entry and on exit.
+// Forward uses exp(-2 pi i nk/M), inverse exp(+2 pi i nk/M).
+// PAD selects the slot map (lds_slot); a padded transform occupies M + M/16
+// slots (rows of ls slots for PAD = 2).  WAVE: every lane sharing the LDS
+// regions is in the calling wave (see xsync); otherwise the whole block must
+// call.  The pass twiddles come from the table tw, or from a lane's
+// preloaded fft_twiddles<M>.
+template <int M, bool INV, int NT, int PAD, bool WAVE, typename L>
+__device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride, int ls,
+                                          int j, const cd* __restrict__ tw) {
+  fft_multi_impl<M, INV, NT, PAD, WAVE>(reg, lds, tstride, ls, j, tw);
+}
+
 template <int M, bool INV, int PAD, bool WAVE, typename L>
 __device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
                                     const cd* __restrict__ tw) {
-  fft_multi<M, INV, 1, PAD, WAVE>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);
+  fft_multi_impl<M, INV, 1, PAD, WAVE>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);
+}
+
+template <int M, bool INV, int PAD, bool WAVE, typename L>
+__device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
+                                    const fft_twiddles<M>& tw) {
+  fft_multi_impl<M, INV, 1, PAD, WAVE>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j,
+                                       &tw);
 }
 
 }  // namespace ssfm

@@ -1,5 +1,5 @@
 // Device helpers shared by the forward and adjoint kernels of libssfm:
-// complex64 <-> FP64 conversion at the HBM boundary, the unit phasor of the
+// complex64 <-> FP64 conversion at the HBM boundary, the unit phasors of the
 // nonlinear step and the four-step twiddle lookup.
 #pragma once
 
@@ -23,29 +23,69 @@ __device__ __forceinline__ cd round_c64(cd v) {
 // exp(i phi) in FP64.  For |phi| <= 1/4 (the nonlinear phase of one split
 // step is ~1e-2 rad on the workloads here) the Taylor series of sin to phi^11
 // and cos to phi^10, truncation below 1e-15 relative, so the rotation is
-// unit-modulus to FP64 rounding.  Larger angles: single-precision sine and
-// cosine, then one Newton step on the modulus in FP64 (a rotation whose
-// modulus carries a single-precision rounding would bias the power at every
-// step).
-__device__ __forceinline__ cd unit_phasor(double phi) {
-  if (fabs(phi) <= 0.25) {
-    const double x2 = phi * phi;
-    double ps = fma(x2, -1.0 / 39916800.0, 1.0 / 362880.0);
-    ps = fma(ps, x2, -1.0 / 5040.0);
-    ps = fma(ps, x2, 1.0 / 120.0);
-    ps = fma(ps, x2, -1.0 / 6.0);
-    double pc = fma(x2, -1.0 / 3628800.0, 1.0 / 40320.0);
-    pc = fma(pc, x2, -1.0 / 720.0);
-    pc = fma(pc, x2, 1.0 / 24.0);
-    pc = fma(pc, x2, -0.5);
-    return {fma(pc, x2, 1.0), fma(ps * x2, phi, phi)};
+// unit-modulus to FP64 rounding.
+__device__ __forceinline__ cd phasor_series(double phi) {
+  const double x2 = phi * phi;
+  double ps = fma(x2, -1.0 / 39916800.0, 1.0 / 362880.0);
+  ps = fma(ps, x2, -1.0 / 5040.0);
+  ps = fma(ps, x2, 1.0 / 120.0);
+  ps = fma(ps, x2, -1.0 / 6.0);
+  double pc = fma(x2, -1.0 / 3628800.0, 1.0 / 40320.0);
+  pc = fma(pc, x2, -1.0 / 720.0);
+  pc = fma(pc, x2, 1.0 / 24.0);
+  pc = fma(pc, x2, -0.5);
+  return {fma(pc, x2, 1.0), fma(ps * x2, phi, phi)};
+}
+
+// Any angle: the series at phi / 2^k (halved until |phi / 2^k| <= 1/4),
+// squared k times, then one Newton step on the modulus (k squarings double
+// the relative rounding error k times).  For |phi| <= 1/4 it returns the
+// series' bits unchanged.  Reads no memory.
+__device__ __forceinline__ cd unit_phasor_any(double phi) {
+  int k = 0;
+#pragma unroll 1
+  while (fabs(phi) > 0.25 && k < 1100) {  // any finite angle needs < 1030
+    phi *= 0.5;
+    ++k;
   }
-  float s, c;
-  sincosf((float)phi, &s, &c);
-  const double cr = c, sr = s;
-  const double m = fma(cr, cr, sr * sr);
+  cd z = phasor_series(phi);
+  if (k == 0) return z;
+#pragma unroll 1
+  for (int i = 0; i < k; ++i) z = {(z.re - z.im) * (z.re + z.im), 2.0 * z.re * z.im};
+  const double m = fma(z.re, z.re, z.im * z.im);
   const double f = fma(-0.5, m, 1.5);
-  return {cr * f, sr * f};
+  return {z.re * f, z.im * f};
+}
+
+// rot[r] = exp(i phi[r]), r < 16, out of line: only waves holding a large
+// angle call it, and its registers do not count against the callers'.
+__device__ __noinline__ void unit_phasors_any16(const double* phi, cd* rot) {
+#pragma unroll 1
+  for (int r = 0; r < 16; ++r) rot[r] = unit_phasor_any(phi[r]);
+}
+
+// f(r, exp(i phi[r])) for the 16 angles of a lane.  The branch is uniform
+// over the wave: the series unless some angle of the wave exceeds 1/4, and
+// both branches give the same bits for the small angles, so a result never
+// depends on its neighbours.  (A per-element branch makes the compiler keep
+// registers for both paths across 16 divergent regions.)
+template <typename F>
+__device__ __forceinline__ void for_each_phasor16(const double (&phi)[16], F&& f) {
+  bool big = false;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) big |= !(fabs(phi[r]) <= 0.25);
+  if (__any(big)) {
+    double ph[16];
+    cd rot[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ph[r] = phi[r];
+    unit_phasors_any16(ph, rot);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) f(r, rot[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) f(r, phasor_series(phi[r]));
+  }
 }
 
 // twiddle W_N^m from the two-level table (m < N): twA[a] = W_N^{a N2},

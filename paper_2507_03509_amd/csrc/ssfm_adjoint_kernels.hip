@@ -69,17 +69,24 @@ __global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
     for (int r = 0; r < 16; ++r) lds[((f * P + p) * N1 + j + T * r) * C + c] = reg[r];
     __syncthreads();
     constexpr int F = N1 * C;  // one field-polarisation plane
+    double phi[16];
+    if (f == 0) {
+      // x = y e^{-i phi}; the power is one add of per-polarisation terms
+      // (commutative, so every lane of the sample gets the same phase)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = (j + T * r) * C + c;
-      if (f == 0) {
-        // x = y e^{-i phi}; the power is one add of per-polarisation terms
-        // (commutative, so every lane of the sample gets the same phase)
+      for (int r = 0; r < 16; ++r) {
+        const int i = (j + T * r) * C + c;
         double pw = norm2(reg[r]);
         if constexpr (P == 2) pw = pw + norm2(lds[(1 - p) * F + i]);
-        reg[r] = cmul(reg[r], unit_phasor(-a.kappa * pw));
-      } else {
-        // g_x = g_y e^{-i phi} + 2 s kappa x,  s = -Im sum_q conj(g_q) y_q
+        phi[r] = -a.kappa * pw;
+      }
+      for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
+    } else {
+      // g_x = g_y e^{-i phi} + 2 s kappa x,  s = -Im sum_q conj(g_q) y_q
+      double w[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = (j + T * r) * C + c;
         const cd yp = lds[p * F + i];
         double pw = norm2(yp);
         double s = fma(reg[r].im, yp.re, -reg[r].re * yp.im);
@@ -89,12 +96,14 @@ __global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
           pw = pw + norm2(yo);
           s = fma(go.im, yo.re, fma(-go.re, yo.im, s));
         }
-        const cd e = unit_phasor(-a.kappa * pw);  // e^{-i phi}
-        const cd x = cmul(yp, e);
-        const cd gx = cmul(reg[r], e);
-        const double w = 2.0 * s * a.kappa;
-        reg[r] = {fma(w, x.re, gx.re), fma(w, x.im, gx.im)};
+        phi[r] = -a.kappa * pw;
+        w[r] = 2.0 * s * a.kappa;
       }
+      for_each_phasor16(phi, [&](int r, cd e) {  // e = e^{-i phi}
+        const cd x = cmul(lds[p * F + (j + T * r) * C + c], e);
+        const cd gx = cmul(reg[r], e);
+        reg[r] = {fma(w[r], x.re, gx.re), fma(w[r], x.im, gx.im)};
+      });
     }
     fft<N1, false, 2, false>(reg, mylds, C, j, a.tw1);
   }

@@ -126,18 +126,19 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
         for (int r = 0; r < 16; ++r)
           pbuf[p * (N1 * C) + (j + T * r) * C + c] = fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im);
         __syncthreads();
+        double phi[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int i = (j + T * r) * C + c;
-          const double pw = pbuf[i] + pbuf[N1 * C + i];
-          reg[r] = cmul(reg[r], unit_phasor(a.kappa * pw));
+          phi[r] = a.kappa * (pbuf[i] + pbuf[N1 * C + i]);
         }
+        for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
       } else {
+        double phi[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const double pw = fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im);
-          reg[r] = cmul(reg[r], unit_phasor(a.kappa * pw));
-        }
+        for (int r = 0; r < 16; ++r)
+          phi[r] = a.kappa * fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im);
+        for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
       }
     } else {
       // amplifier: a <- gspan a + ASE(t), t = n1 N2 + n2.  The noise is drawn
@@ -211,15 +212,18 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
       if (i > 0) {
         // nonlinear phase of step i-1
         const double kap = a.kappa[i - 1];
+        double phi[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           double pw = 0.0;
 #pragma unroll
           for (int q = 0; q < P; ++q) pw = fma(reg[q][r].re, reg[q][r].re, fma(reg[q][r].im, reg[q][r].im, pw));
-          const cd rot = unit_phasor(kap * pw);
+          phi[r] = kap * pw;
+        }
+        for_each_phasor16(phi, [&](int r, cd rot) {
 #pragma unroll
           for (int q = 0; q < P; ++q) reg[q][r] = cmul(reg[q][r], rot);
-        }
+        });
       }
       const cd* h = (i == 0 || i == a.steps) ? a.h_half : a.h_full;
       fft_multi<N, false, P, true, false>(reg, lds1, N + N / 16, 1, jj, a.tw);

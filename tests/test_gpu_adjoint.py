@@ -105,3 +105,16 @@ def test_adjoint_rejects_lds_path(ssfm):
         plan.adjoint(x, g)
     assert e.value.status == ssfm.SSFM_EUNSUPPORTED
     plan.close()
+
+
+@pytest.mark.parametrize("n,n_pol", [(1 << 14, 2), (1 << 15, 1)])
+def test_adjoint_large_nonlinear_phase(ssfm, n, n_pol):
+    # 18 dBm over 20 km steps: per-step phases of several rad on most samples
+    print(f"case n={n} n_pol={n_pol}", flush=True)
+    rng = np.random.default_rng(n + n_pol)
+    ln = link(n_pol, n, spans=1, steps=4)
+    x = dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 18.0)
+    g = dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 0.0)
+    got, _ = gpu_adjoint(ssfm, x[None], g[None], ln, seed=3)
+    want = oracle.adjoint(x, g, ln, seed=3)
+    assert rel(got[0], want) < 1e-5, rel(got[0], want)

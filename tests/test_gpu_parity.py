@@ -241,3 +241,32 @@ def test_workload3_full(ssfm):
     err = rel(got, want)
     print(f"workload3 rel_err={err:.3e}", flush=True)
     assert err < TOL
+
+
+# ---------------------------------------------------------------------------
+# per-step nonlinear phases above 1/4 rad (the general phasor branch): 18 dBm
+# over 20 km steps gives up to ~4-7 rad per step on most samples
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,n_pol", [(2048, 2), (2048, 1), (1 << 15, 2), (1 << 15, 1)])
+def test_large_nonlinear_phase(ssfm, n, n_pol):
+    print(f"case n={n} n_pol={n_pol}", flush=True)
+    rng = np.random.default_rng(n + n_pol)
+    a0 = dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 18.0)
+    alpha = 0.2 * math.log(10) / 10 / 1e3
+    h = 80e3 / 4
+    kappa0 = (8 / 9 if n_pol == 2 else 1.0) * 1.3e-3 * 2 * math.sinh(alpha * h / 2) / alpha \
+        * math.exp(-alpha * h / 2)
+    assert kappa0 * np.sum(np.abs(a0) ** 2, axis=0).max() > 2.0
+    # dispersive link against the oracle
+    ln = link(n_pol, n, spans=1, steps=4)
+    got = run_gpu(ssfm, a0[None], ln, seed=3)[0]
+    want = oracle.propagate(a0, ln, seed=3)
+    assert rel(got, want) < TOL, rel(got, want)
+    # nonlinear phase only: the closed form
+    ln = link(n_pol, n, spans=2, steps=4, beta2_ps2_per_km=0.0, ase=False)
+    got = run_gpu(ssfm, a0[None], ln)[0]
+    leff = (1 - 10 ** (-1.6)) / alpha
+    cnl = 8 / 9 if n_pol == 2 else 1.0
+    want = a0 * np.exp(1j * cnl * 1.3e-3 * leff * 2 * np.sum(np.abs(a0) ** 2, axis=0))
+    assert rel(got, want) < TOL, rel(got, want)
