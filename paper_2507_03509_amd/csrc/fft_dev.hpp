@@ -384,4 +384,26 @@ __device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
                                        &tw);
 }
 
+// The twiddle source of a kernel's transforms: the lane's pass twiddles in
+// registers when there are at most two of them (read right after the
+// kernel's field loads, so no transform waits on a table read behind other
+// loads), else the table.
+template <int M, bool PRE = (fft_twiddles<M>::count <= 2)>
+struct lane_twiddles {
+  fft_twiddles<M> t;
+  __device__ __forceinline__ lane_twiddles(const cd* __restrict__ tw, int j) { t.load(tw, j); }
+};
+template <int M>
+struct lane_twiddles<M, false> {
+  const cd* tw;
+  __device__ __forceinline__ lane_twiddles(const cd* __restrict__ table, int) : tw(table) {}
+};
+
+template <int M, bool INV, int PAD, bool WAVE, typename L, bool PRE>
+__device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
+                                    const lane_twiddles<M, PRE>& lt) {
+  if constexpr (PRE) fft<M, INV, PAD, WAVE>(reg, lds, ls, j, lt.t);
+  else fft<M, INV, PAD, WAVE>(reg, lds, ls, j, lt.tw);
+}
+
 }  // namespace ssfm

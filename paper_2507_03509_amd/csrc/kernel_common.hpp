@@ -14,6 +14,36 @@ __device__ __forceinline__ cd load_c64(const float2* p) {
 __device__ __forceinline__ void store_c64(float2* p, cd v) {
   *p = make_float2((float)v.re, (float)v.im);
 }
+// Strided access to the elements j + T r (r < 16) of a lane's column through
+// a buffer resource: a wave-uniform base address in scalar registers, one
+// 32-bit lane offset, and a wave-uniform byte step per element, so the 16
+// loads and stores of a lane share one address register (64-bit addresses
+// would take 32).  The hardware returns zero for loads, and drops stores, at
+// or beyond `bytes` from the base.  Word 3 of the resource selects the 32-bit
+// data format (field 15..18 = 4) that untyped buffer loads need on this chip
+// family.
+struct col_buf {
+  __amdgpu_buffer_rsrc_t rs;
+  uint32_t lane, step;
+};
+__device__ __forceinline__ col_buf make_col_buf(const float2* base, uint32_t bytes, uint32_t lane,
+                                                uint32_t step) {
+  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), (short)0, (int)bytes,
+                                            0x00020000),
+          lane, step};
+}
+__device__ __forceinline__ cd col_load(const col_buf& b, int r) {
+  const float2 v = __builtin_bit_cast(
+      float2, __builtin_amdgcn_raw_buffer_load_b64(b.rs, b.lane, (uint32_t)r * b.step, 0));
+  return {(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void col_store(const col_buf& b, int r, cd v) {
+  using raw64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(b.rs, 0, 0, 0));
+  const float2 f = make_float2((float)v.re, (float)v.im);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(raw64, f), b.rs, b.lane,
+                                        (uint32_t)r * b.step, 0);
+}
+
 // The state at a span boundary is the complex64 field: rounding to it there
 // makes a run split at span boundaries identical, bit for bit, to one call.
 __device__ __forceinline__ cd round_c64(cd v) {

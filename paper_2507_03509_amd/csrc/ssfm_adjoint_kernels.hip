@@ -55,11 +55,12 @@ __global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
   cd reg[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) reg[r] = load_c64(src + (int64_t)(j + T * r) * a.n2);
+  const cd* __restrict__ ltw = a.tw1;
 
   if constexpr (AMODE == AMODE_FIRST) {
-    fft<N1, false, 2, false>(reg, mylds, C, j, a.tw1);
+    fft<N1, false, 2, false>(reg, mylds, C, j, ltw);
   } else if constexpr (AMODE == AMODE_NL) {
-    fft<N1, true, 2, false>(reg, mylds, C, j, a.tw1);
+    fft<N1, true, 2, false>(reg, mylds, C, j, ltw);
     // exchange in natural (row, column) order: every lane publishes its
     // value and reads only those it does not hold (state lanes: the other
     // polarisation's state; cotangent lanes: both states and the other
@@ -105,12 +106,12 @@ __global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
         reg[r] = {fma(w[r], x.re, gx.re), fma(w[r], x.im, gx.im)};
       });
     }
-    fft<N1, false, 2, false>(reg, mylds, C, j, a.tw1);
+    fft<N1, false, 2, false>(reg, mylds, C, j, ltw);
   }
   if constexpr (AMODE == AMODE_LAST) {
     // every lane transforms (the block barriers need all of them); only the
     // cotangent is stored, the state is not needed past the span start
-    fft<N1, true, 2, false>(reg, mylds, C, j, a.tw1);
+    fft<N1, true, 2, false>(reg, mylds, C, j, ltw);
     if (f == 0) return;
 #pragma unroll
     for (int r = 0; r < 16; ++r) reg[r] = round_c64(cscale(reg[r], a.gspan));

@@ -37,7 +37,7 @@ namespace ssfm {
 // K2: rows of length N2 (contiguous), WG lanes, FP32 LDS exchange.
 // ---------------------------------------------------------------------------
 template <int N2, int WG, typename L, bool CONJ>
-__global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field, const cd* __restrict__ H,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void k2_rows(float2* __restrict__ field, const cd* __restrict__ H,
                                               const cd* __restrict__ tw,
                                               const cd* __restrict__ twA,
                                               const cd* __restrict__ twB, int n1, int log2_n2) {
@@ -54,6 +54,7 @@ __global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field, const 
   cd reg[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) reg[r] = load_c64(rp + j + T * r);
+  const lane_twiddles<N2> ltw(tw, j);
   // four-step twiddle W_N^{n2 k1} on n2 = j + T r: W_N^{k1 j} (W_N^{k1 T})^r
   const cd w0 = four_step_twiddle(twA, twB, k1 * j, log2_n2, N2);
   const cd wstep = four_step_twiddle(twA, twB, k1 * T, log2_n2, N2);
@@ -65,12 +66,12 @@ __global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field, const 
       if (r < 15) w = cmul(w, wstep);
     }
   }
-  fft<N2, false, true, true>(reg, mylds, 1, j, tw);  // one wave per row
+  fft<N2, false, true, true>(reg, mylds, 1, j, ltw);  // one wave per row
   const cd* hp = H + (int64_t)k1 * N2;
   // CONJ: conj(H), the adjoint (and inverse) of the unitary linear step
 #pragma unroll
   for (int r = 0; r < 16; ++r) reg[r] = cmul_t<CONJ>(reg[r], hp[j + T * r]);
-  fft<N2, true, true, true>(reg, mylds, 1, j, tw);
+  fft<N2, true, true, true>(reg, mylds, 1, j, ltw);
   {
     cd w = w0;
 #pragma unroll
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(WG) void k2_rows(float2* __restrict__ field, const 
 
 
 template <int N1, int C, int P, int MODE, typename L>
-__global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
+__global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_eu(2, 2))) void k3_cols(ColArgs a) {
   constexpr int T = N1 / 16;
   extern __shared__ __align__(16) unsigned char lds3_raw[];
   L* lds3 = reinterpret_cast<L*>(lds3_raw);
@@ -106,16 +107,23 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
   const unsigned G = gridDim.x;
   const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
   const int64_t b = id / tiles;
-  const int n2 = (int)(id % tiles) * C + c;
-  float2* fp = a.field + (b * P + p) * a.n + n2;
+  const int col0 = (int)(id % tiles) * C;
+  const int n2 = col0 + c;
+  // this tile's realisation from column col0 on; lane element r at
+  // (p n + c + (j + T r) n2) complex64 slots
+  const uint32_t tile_bytes = (uint32_t)((P * a.n - col0) * 8);
+  const uint32_t lane_off = (uint32_t)(p * a.n + c + (int64_t)j * a.n2) * 8u;
+  const uint32_t step = (uint32_t)(T * a.n2) * 8u;
+  const col_buf fb = make_col_buf(a.field + b * P * a.n + col0, tile_bytes, lane_off, step);
   L* mylds = lds3 + p * (N1 * C) + c;
   cd reg[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) reg[r] = load_c64(fp + (int64_t)(j + T * r) * a.n2);
+  for (int r = 0; r < 16; ++r) reg[r] = col_load(fb, r);
+  const lane_twiddles<N1> ltw(a.tw1, j);
 
   if constexpr (MODE != MODE_FIRST) {
     // mixed (k1, n2) domain -> time: inverse column FFT
-    fft<N1, true, false, false>(reg, mylds, C, j, a.tw1);
+    fft<N1, true, false, false>(reg, mylds, C, j, ltw);
     if constexpr (MODE == MODE_NL) {
       if constexpr (P == 2) {
         // exchange |a_p|^2 with the lane of the other polarisation (the sum
@@ -150,9 +158,9 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
       const bool noisy = a.sigma_h != 0.0;
       if (a.ckpt) {
         // span-end state before the amplifier, for the adjoint
-        float2* cp = a.ckpt + (b * P + p) * a.n + n2;
+        const col_buf cb = make_col_buf(a.ckpt + b * P * a.n + col0, tile_bytes, lane_off, step);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) store_c64(cp + (int64_t)(j + T * r) * a.n2, reg[r]);
+        for (int r = 0; r < 16; ++r) col_store(cb, r, reg[r]);
       }
       float2* nbuf = reinterpret_cast<float2*>(lds3_raw) + p * (N1 * C) + c;
       if (noisy) {
@@ -178,10 +186,10 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) void k3_cols(ColArgs a) {
   }
   if constexpr (MODE != MODE_LAST) {
     // time -> mixed domain: column FFT
-    fft<N1, false, false, false>(reg, mylds, C, j, a.tw1);
+    fft<N1, false, false, false>(reg, mylds, C, j, ltw);
   }
 #pragma unroll
-  for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
+  for (int r = 0; r < 16; ++r) col_store(fb, r, reg[r]);
 }
 
 // ---------------------------------------------------------------------------
