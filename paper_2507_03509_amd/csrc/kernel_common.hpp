@@ -44,6 +44,15 @@ __device__ __forceinline__ void col_store(const col_buf& b, int r, cd v) {
                                         (uint32_t)r * b.step, 0);
 }
 
+// A pointer that the caller knows to be equal on every lane of the wave, moved
+// to scalar registers (a buffer resource must be).
+__device__ __forceinline__ const float2* wave_uniform(const float2* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const float2*>(((uint64_t)hi << 32) | lo);
+}
+
 // The state at a span boundary is the complex64 field: rounding to it there
 // makes a run split at span boundaries identical, bit for bit, to one call.
 __device__ __forceinline__ cd round_c64(cd v) {

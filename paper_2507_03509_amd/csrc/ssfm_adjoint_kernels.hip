@@ -28,7 +28,8 @@ __device__ __forceinline__ double norm2(cd v) { return fma(v.re, v.re, v.im * v.
 //                because everything in between is linear in the cotangent)
 // ---------------------------------------------------------------------------
 template <int N1, int C, int P, int AMODE>
-__global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
+__global__ __launch_bounds__(2 * P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k3_adj(AdjArgs a) {
   constexpr int T = N1 / 16;
   extern __shared__ __align__(16) unsigned char lds_adj[];
   cd* lds = reinterpret_cast<cd*>(lds_adj);
@@ -43,19 +44,37 @@ __global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
   const unsigned G = gridDim.x;
   const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
   const int64_t b = id / tiles;
-  const int n2 = (int)(id % tiles) * C + c;
-  float2* fp = a.work + ((f * a.batch + b) * P + p) * a.n + n2;
+  const int col0 = (int)(id % tiles) * C;
+  const int n2 = col0 + c;
   // FFT regions: one per (field, polarisation), N1 + N1/16 padded rows of C
   constexpr int RS = (N1 + N1 / 16) * C;
   cd* mylds = lds + (f * P + p) * RS + c;
-  const float2* src = fp;
+  // Field f of a wave is one value when a field's lanes fill whole waves:
+  // then the tile is addressed through buffer resources (wave-uniform base,
+  // one lane offset), else through per-element 64-bit addresses.
+  constexpr bool WAVE_F = (P * C * T) % 64 == 0;
+  const float2* rbase = a.work + (f * a.batch + b) * P * a.n + col0;  // realisation, column col0
+  const float2* sbase = rbase;
   if constexpr (AMODE == AMODE_FIRST) {
-    if (f == 0) src = a.ckpt + (b * P + p) * a.n + n2;
+    if (f == 0) sbase = a.ckpt + b * P * a.n + col0;
   }
+  const uint32_t tile_bytes = (uint32_t)((P * a.n - col0) * 8);
+  const uint32_t lane_off = (uint32_t)(p * a.n + c + (int64_t)j * a.n2) * 8u;
+  const uint32_t step = (uint32_t)(T * a.n2) * 8u;
+  col_buf fb{}, sb{};
+  if constexpr (WAVE_F) {
+    fb = make_col_buf(wave_uniform(rbase), tile_bytes, lane_off, step);
+    sb = make_col_buf(wave_uniform(sbase), tile_bytes, lane_off, step);
+  }
+  float2* fp = const_cast<float2*>(rbase) + p * a.n + c;
+  const float2* src = sbase + p * a.n + c;
   cd reg[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) reg[r] = load_c64(src + (int64_t)(j + T * r) * a.n2);
-  const cd* __restrict__ ltw = a.tw1;
+  for (int r = 0; r < 16; ++r) {
+    if constexpr (WAVE_F) reg[r] = col_load(sb, r);
+    else reg[r] = load_c64(src + (int64_t)(j + T * r) * a.n2);
+  }
+  const lane_twiddles<N1> ltw(a.tw1, j);
 
   if constexpr (AMODE == AMODE_FIRST) {
     fft<N1, false, 2, false>(reg, mylds, C, j, ltw);
@@ -84,26 +103,28 @@ __global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
       for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
     } else {
       // g_x = g_y e^{-i phi} + 2 s kappa x,  s = -Im sum_q conj(g_q) y_q
-      double w[16];
+      // (the states and the other cotangent are read from LDS again in the
+      // second loop rather than held in registers)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = (j + T * r) * C + c;
+        double pw = norm2(lds[p * F + i]);
+        if constexpr (P == 2) pw = pw + norm2(lds[(1 - p) * F + i]);
+        phi[r] = -a.kappa * pw;
+      }
+      for_each_phasor16(phi, [&](int r, cd e) {  // e = e^{-i phi}
+        const int i = (j + T * r) * C + c;
         const cd yp = lds[p * F + i];
-        double pw = norm2(yp);
         double s = fma(reg[r].im, yp.re, -reg[r].re * yp.im);
         if constexpr (P == 2) {
           const cd yo = lds[(1 - p) * F + i];
           const cd go = lds[(P + 1 - p) * F + i];
-          pw = pw + norm2(yo);
           s = fma(go.im, yo.re, fma(-go.re, yo.im, s));
         }
-        phi[r] = -a.kappa * pw;
-        w[r] = 2.0 * s * a.kappa;
-      }
-      for_each_phasor16(phi, [&](int r, cd e) {  // e = e^{-i phi}
-        const cd x = cmul(lds[p * F + (j + T * r) * C + c], e);
+        const double w = 2.0 * s * a.kappa;
+        const cd x = cmul(yp, e);
         const cd gx = cmul(reg[r], e);
-        reg[r] = {fma(w[r], x.re, gx.re), fma(w[r], x.im, gx.im)};
+        reg[r] = {fma(w, x.re, gx.re), fma(w, x.im, gx.im)};
       });
     }
     fft<N1, false, 2, false>(reg, mylds, C, j, ltw);
@@ -117,7 +138,10 @@ __global__ __launch_bounds__(2 * P * C * (N1 / 16)) void k3_adj(AdjArgs a) {
     for (int r = 0; r < 16; ++r) reg[r] = round_c64(cscale(reg[r], a.gspan));
   }
 #pragma unroll
-  for (int r = 0; r < 16; ++r) store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
+  for (int r = 0; r < 16; ++r) {
+    if constexpr (WAVE_F) col_store(fb, r, reg[r]);
+    else store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
+  }
 }
 
 // ---------------------------------------------------------------------------
