@@ -51,7 +51,7 @@ Geometry make_geometry(int64_t n, int tile, int halo, int arrays, int n_pol, int
   g.halo = halo;
   g.region = round_up(g.w + 2 * halo, L::R);
   g.ls = L::region_stride(g.region);
-  g.tiles = (int)(n / g.w);
+  g.tiles = (int)((n + g.w - 1) / g.w);  // the last tile of a row may be shorter
   g.threads = round_up(g.region / L::R, 64);
   g.lds = (size_t)arrays * n_pol * g.ls * sizeof(cd) + (size_t)extra_lds;
   return g;
@@ -107,6 +107,8 @@ struct ssfm_ldbp_s {
   Geometry bwd_geom() const {
     const int s = d.steps_per_span;
     const int halo = L::HC * std::max(s, 2 * (s - 1));
+    // (tiles of bwd_tile - 2 halo, whose regions fill whole waves, measured
+    // slower: two workgroups of two waves per CU instead of two of three)
     Geometry g = make_geometry(d.n_samples, bwd_tile, halo, s + 1, d.n_pol, 0);
     g.lds += (size_t)(g.threads / 64) * sizeof(double);  // reduction scratch
     return g;

@@ -184,6 +184,7 @@ __global__ __launch_bounds__(1024) void ldbp_fwd(FwdArgs a, const cd* __restrict
   const int tile = (int)(blockIdx.x % a.tiles);
   const int64_t n0 = (int64_t)tile * a.w - a.halo;
   const int64_t nm = a.n - 1;
+  const int wt = (int)min((int64_t)a.w, a.n - (int64_t)tile * a.w);  // interior samples
   const float2* src = a.src + b * P * a.n;
   zero_guards(st, P, a.ls, a.region);
   for (int i = tid; i < a.region; i += blockDim.x) {
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(1024) void ldbp_fwd(FwdArgs a, const cd* __restrict
     if (a.ckpt && span_end && k + 1 < a.k1) {
       float2* cp = a.ckpt + ((int64_t)((k + 1) / a.spans_steps - 1) * a.batch + b) * P * a.n +
                    (int64_t)tile * a.w;
-      for (int i = tid; i < a.w; i += blockDim.x) {
+      for (int i = tid; i < wt; i += blockDim.x) {
 #pragma unroll
         for (int pp = 0; pp < P; ++pp)
           store_c64(cp + pp * a.n + i, st[pp * a.ls + lslot(a.halo + i)]);
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(1024) void ldbp_fwd(FwdArgs a, const cd* __restrict
     }
   }
   float2* dst = a.dst + b * P * a.n + (int64_t)tile * a.w;
-  for (int i = tid; i < a.w; i += blockDim.x) {
+  for (int i = tid; i < wt; i += blockDim.x) {
 #pragma unroll
     for (int pp = 0; pp < P; ++pp) store_c64(dst + pp * a.n + i, st[pp * a.ls + lslot(a.halo + i)]);
   }
@@ -349,6 +350,8 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
   const int64_t n0 = (int64_t)tile * a.w - a.halo;
   const int64_t nm = a.n - 1;
   const int64_t row0 = b * P * a.n;
+  // interior samples of this tile (the row's last tile may be shorter)
+  const int wt = (int)min((int64_t)a.w, a.n - (int64_t)tile * a.w);
   zero_guards(xs_lds, P * (a.s_steps + 1), a.ls, a.region);
   for (int i = tid; i < a.region; i += blockDim.x) {
 #pragma unroll
@@ -413,7 +416,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
           gy[p][r] = {fma(w2, y.re, ge.re), fma(w2, y.im, ge.im)};
         }
         const int i = base + r;
-        if (i >= a.halo && i < a.halo + a.w) xi_part = fma(pw, s, xi_part);
+        if (i >= a.halo && i < a.halo + wt) xi_part = fma(pw, s, xi_part);
       }
     }
     __syncthreads();  // earlier readers of G are done
@@ -445,7 +448,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
       }
     }
     double* part = a.partial + ((int64_t)k * gridDim.x + blockIdx.x) * NRED;
-    tap_gradient<P>(G, X, a.ls, a.halo, a.w, part);
+    tap_gradient<P>(G, X, a.ls, a.halo, wt, part);
     // dL/dxi: one value, summed over the workgroup
     block_sum1(xi_part, red, part + 2 * TAPS);
   }
@@ -455,7 +458,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = base + r;
-        if (i >= a.halo && i < a.halo + a.w) store_c64(a.g_out + row0 + p * a.n + (n0 + i), g[p][r]);
+        if (i >= a.halo && i < a.halo + wt) store_c64(a.g_out + row0 + p * a.n + (n0 + i), g[p][r]);
       }
   }
 }
