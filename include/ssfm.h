@@ -159,9 +159,11 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
  * everything but the span count are propagated together: gathered into one
  * stream-ordered staging buffer, most spans first, and run over span
  * segments on the shrinking prefix of entries still propagating; plans are
- * built on first use and cached for the life of the process.  links, fields
- * and seeds are host arrays; the call is asynchronous on `stream` of device
- * `hip_device`.  Errors: SSFM_EINVAL (invalid link, NULL or misaligned
+ * built on first use and cached for the life of the process.  Such groups
+ * run concurrently on up to four worker streams of the device (created on
+ * first use, kept for the life of the process), forked from `stream` and
+ * joined back into it with events.  links, fields and seeds are host
+ * arrays; the call is asynchronous on `stream` of device `hip_device`.  Errors: SSFM_EINVAL (invalid link, NULL or misaligned
  * pointer, count < 1), SSFM_ENOMEM, SSFM_EHIP. */
 int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
                const uint64_t* seeds, int hip_device, void* stream);

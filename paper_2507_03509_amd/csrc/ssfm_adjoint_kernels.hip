@@ -45,7 +45,6 @@ void k3_adj(AdjArgs a) {
   const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
   const int64_t b = id / tiles;
   const int col0 = (int)(id % tiles) * C;
-  const int n2 = col0 + c;
   // FFT regions: one per (field, polarisation), N1 + N1/16 padded rows of C
   constexpr int RS = (N1 + N1 / 16) * C;
   cd* mylds = lds + (f * P + p) * RS + c;

@@ -453,6 +453,31 @@ PlanCache& plan_cache() {
   return *c;
 }
 
+// Worker streams of ssfm_batch, per device, created on first use and kept
+// for the life of the process (default priority, not blocking on the null
+// stream; every use is ordered against the caller's stream by events).
+constexpr int kBatchStreams = 4;
+struct BatchStreams {
+  hipStream_t s[kBatchStreams] = {};
+};
+int batch_streams(int device, hipStream_t (&out)[kBatchStreams]) {
+  static std::mutex mu;
+  static std::map<int, BatchStreams>* per = new std::map<int, BatchStreams>();
+  std::lock_guard<std::mutex> lock(mu);
+  BatchStreams& b = (*per)[device];
+  for (int k = 0; k < kBatchStreams; ++k) {
+    if (!b.s[k]) {
+      const hipError_t e = hipStreamCreateWithFlags(&b.s[k], hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        b.s[k] = nullptr;
+        return api_fail_hip(e, "ssfm_batch worker stream");
+      }
+    }
+    out[k] = b.s[k];
+  }
+  return SSFM_OK;
+}
+
 }  // namespace
 
 extern "C" int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out);
@@ -736,10 +761,51 @@ int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
     }
     groups[gi].push_back(i);
   }
+  // Groups are independent: they run concurrently on worker streams forked
+  // from (and joined back into) the caller's stream.  An LDS-resident group
+  // keeps one workgroup per realisation busy for the whole link and fills
+  // only as many CUs as it has realisations, so groups are placed, largest
+  // estimated time first, on the least-loaded stream.
+  std::vector<ssfm_plan_t> plans(groups.size());
+  std::vector<double> cost(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) {
-    ssfm_plan_t plan = nullptr;
-    int rc = cached_plan(keys[gi], hip_device, &plan);
+    const int rc = cached_plan(keys[gi], hip_device, &plans[gi]);
     if (rc != SSFM_OK) return rc;
+    const ssfm_plan_s* pl = plans[gi];
+    int max_spans = 0;
+    double span_sum = 0.0;
+    for (int64_t i : groups[gi]) {
+      max_spans = std::max(max_spans, links[i].n_spans);
+      span_sum += links[i].n_spans;
+    }
+    // LDS path: latency of the longest realisation; four-step: total work
+    cost[gi] = pl->ks.path == 1 ? 4.0 * max_spans * pl->steps * (double)pl->n * pl->n_pol
+                                : span_sum * pl->steps * (double)pl->n * pl->n_pol / 16.0;
+  }
+  std::vector<size_t> order(groups.size());
+  for (size_t gi = 0; gi < order.size(); ++gi) order[gi] = gi;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  hipStream_t ws[kBatchStreams];
+  int rc = batch_streams(hip_device, ws);
+  if (rc != SSFM_OK) return rc;
+  const int nstreams = (int)std::min<size_t>(kBatchStreams, groups.size());
+  hipEvent_t ev[kBatchStreams + 1] = {};
+  for (int k = 0; k <= nstreams && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev[nstreams], st);  // fork
+  for (int k = 0; k < nstreams && e == hipSuccess; ++k) e = hipStreamWaitEvent(ws[k], ev[nstreams], 0);
+  if (e != hipSuccess) {
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+    return api_fail_hip(e, "ssfm_batch fork");
+  }
+  std::vector<double> load((size_t)nstreams, 0.0);
+  for (size_t oi = 0; oi < order.size() && rc == SSFM_OK && e == hipSuccess; ++oi) {
+    const size_t gi = order[oi];
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[(size_t)k] += cost[gi];
+    hipStream_t gs = ws[k];
+    ssfm_plan_t plan = plans[gi];
     std::vector<int64_t>& idx = groups[gi];
     // most spans first: the realisations still propagating are a prefix
     std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
@@ -750,23 +816,26 @@ int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
     const size_t fbytes = elems * sizeof(float2);
     void* stage = nullptr;
     void* dseeds = nullptr;
-    if ((e = hipMallocAsync(&stage, (size_t)m * fbytes, st)) != hipSuccess)
-      return api_fail(SSFM_ENOMEM, "staging buffer of %zu bytes: %s", (size_t)m * fbytes,
-                  hipGetErrorString(e));
-    if ((e = hipMallocAsync(&dseeds, (size_t)m * sizeof(uint64_t), st)) != hipSuccess) {
-      (void)hipFreeAsync(stage, st);
-      return api_fail(SSFM_ENOMEM, "seed buffer: %s", hipGetErrorString(e));
+    if ((e = hipMallocAsync(&stage, (size_t)m * fbytes, gs)) != hipSuccess) {
+      rc = api_fail(SSFM_ENOMEM, "staging buffer of %zu bytes: %s", (size_t)m * fbytes,
+                    hipGetErrorString(e));
+      break;
+    }
+    if ((e = hipMallocAsync(&dseeds, (size_t)m * sizeof(uint64_t), gs)) != hipSuccess) {
+      (void)hipFreeAsync(stage, gs);
+      rc = api_fail(SSFM_ENOMEM, "seed buffer: %s", hipGetErrorString(e));
+      break;
     }
     std::vector<uint64_t> hseeds((size_t)m);
     for (int64_t r = 0; r < m; ++r) {
       hseeds[(size_t)r] = seeds[idx[(size_t)r]];
       if (e == hipSuccess)
         e = hipMemcpyAsync(static_cast<float2*>(stage) + (size_t)r * elems, fields[idx[(size_t)r]],
-                           fbytes, hipMemcpyDeviceToDevice, st);
+                           fbytes, hipMemcpyDeviceToDevice, gs);
     }
     if (e == hipSuccess)
       e = hipMemcpyAsync(dseeds, hseeds.data(), (size_t)m * sizeof(uint64_t),
-                         hipMemcpyHostToDevice, st);
+                         hipMemcpyHostToDevice, gs);
     // segments of constant active count
     int s0 = 0;
     while (rc == SSFM_OK && e == hipSuccess) {
@@ -774,18 +843,27 @@ int ssfm_batch(const ssfm_link* links, void* const* fields, int64_t count,
       while (active < m && links[idx[(size_t)active]].n_spans > s0) ++active;
       if (active == 0) break;
       const int s1 = links[idx[(size_t)(active - 1)]].n_spans;
-      rc = run_forward(plan, static_cast<float2*>(stage), active, 0, 0, s0, s1, st, nullptr,
+      rc = run_forward(plan, static_cast<float2*>(stage), active, 0, 0, s0, s1, gs, nullptr,
                        static_cast<const uint64_t*>(dseeds));
       s0 = s1;
     }
     for (int64_t r = 0; r < m && rc == SSFM_OK && e == hipSuccess; ++r)
       e = hipMemcpyAsync(fields[idx[(size_t)r]], static_cast<float2*>(stage) + (size_t)r * elems,
-                         fbytes, hipMemcpyDeviceToDevice, st);
-    (void)hipFreeAsync(stage, st);
-    (void)hipFreeAsync(dseeds, st);
-    if (rc != SSFM_OK) return rc;
-    if (e != hipSuccess) return api_fail_hip(e, "ssfm_batch copies");
+                         fbytes, hipMemcpyDeviceToDevice, gs);
+    (void)hipFreeAsync(stage, gs);
+    (void)hipFreeAsync(dseeds, gs);
   }
+  // join: the caller's stream waits for every worker stream (also after an
+  // error, so that no work of this call is left unordered)
+  hipError_t ej = hipSuccess;
+  for (int k = 0; k < nstreams; ++k) {
+    if (ej == hipSuccess) ej = hipEventRecord(ev[k], ws[k]);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(st, ev[k], 0);
+  }
+  for (int k = 0; k <= nstreams; ++k) (void)hipEventDestroy(ev[k]);
+  if (rc != SSFM_OK) return rc;
+  if (e != hipSuccess) return api_fail_hip(e, "ssfm_batch copies");
+  if (ej != hipSuccess) return api_fail_hip(ej, "ssfm_batch join");
   return SSFM_OK;
 }
 
