@@ -18,10 +18,11 @@ __device__ __forceinline__ void store_c64(float2* p, cd v) {
 // a buffer resource: a wave-uniform base address in scalar registers, one
 // 32-bit lane offset, and a wave-uniform byte step per element, so the 16
 // loads and stores of a lane share one address register (64-bit addresses
-// would take 32).  The hardware returns zero for loads, and drops stores, at
-// or beyond `bytes` from the base.  Word 3 of the resource selects the 32-bit
-// data format (field 15..18 = 4) that untyped buffer loads need on this chip
-// family.
+// would take 32).  `bytes` is the resource's range (the hardware's bounds
+// check applies to the lane offset); every caller keeps each access inside
+// its tile, which lies within the range.  Word 3 of the resource selects the
+// 32-bit data format (field 15..18 = 4) that untyped buffer loads need on
+// this chip family.
 struct col_buf {
   __amdgpu_buffer_rsrc_t rs;
   uint32_t lane, step;
