@@ -56,6 +56,9 @@ def parse():
                     help="minimum CPU time of the oracle baseline sample")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="time one forward+adjoint call on the batch (0 to skip)")
+    ap.add_argument("--dft16", action="store_true",
+                    help="time the radix-16 DFT stage prototype: the FFTs' vector "
+                         "butterfly against the matrix-core product (one JSON line)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a "
                          "known-size reference for hardware traffic counters)")
@@ -133,6 +136,60 @@ def cpu_all_cores(workload: int, budget_s: float):
     with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
         list(ex.map(_oracle_realisation, [(workload, r) for r in range(workers)]))
     return workers, time.perf_counter() - t0, workers
+
+
+def bench_dft16(args) -> int:
+    """Radix-16 DFT stage: 2^20 transforms of 16 complex FP64 values, 64
+    rounds each (values through LDS between rounds, as between FFT passes),
+    on the vector butterfly (method 0) and on the FP64 matrix cores
+    (method 1).  Flops counted per transform and round: 5 N log2 N = 320 for
+    the butterfly (the FFT convention) and 2 x 32 x 32 = 2048 for the matrix
+    product (what the matrix cores execute)."""
+    import numpy as np
+    import torch
+
+    import paper_2507_03509_amd as ssfm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    ssfm.load_library()
+    dev = torch.device("cuda:0")
+    count, rounds = 1 << 20, 64
+    rng = np.random.default_rng(16)
+    x = torch.from_numpy(rng.standard_normal((count, 16)) + 1j * rng.standard_normal((count, 16)))
+    data = x.to(dev)
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for method, name in ((0, "valu_butterfly"), (1, "mfma_f64_matrix")):
+        for _ in range(max(1, args.warmup)):
+            ssfm.ssfm_dft16_rounds(method, data, rounds, stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            ssfm.ssfm_dft16_rounds(method, data, rounds, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        per_s = count * rounds / (ms * 1e-3)
+        flops = 320.0 if method == 0 else 2.0 * 32 * 32
+        res[name] = {"ms_per_call": round(ms, 4), "transforms_per_s": per_s,
+                     "tflops": per_s * flops / 1e12}
+        log(f"{name}: {ms:.3f} ms per call, {per_s:.4e} transforms/s, "
+            f"{per_s * flops / 1e12:.1f} TFLOP/s counted")
+    out = {
+        "metric": "radix-16 DFT stage (FP64) transforms/s", "unit": "transforms/s",
+        "value": res["valu_butterfly"]["transforms_per_s"], "higher_is_better": True,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": "dft16 2^20 transforms x 64 rounds"},
+        "methods": res,
+        "mfma_over_valu_time": res["valu_butterfly"]["transforms_per_s"] /
+                               res["mfma_f64_matrix"]["transforms_per_s"],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def bench_mixed_batch(args) -> int:
@@ -336,6 +393,8 @@ def bench_ldbp(args) -> int:
 
 def main() -> int:
     args = parse()
+    if args.dft16 and args.gpus == 1:
+        return bench_dft16(args)
     if args.workload == 4 and args.gpus == 1:
         return bench_mixed_batch(args)
     if args.workload == 5 and args.gpus == 1:

@@ -222,6 +222,22 @@ int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int
  * SSFM_EHIP on a launch failure. */
 int ssfm_stream_copy(void* dst, const void* src, int64_t bytes, void* stream);
 
+/* Radix-16 DFT stage on the FP64 matrix cores against the FP64 vector
+ * butterfly of the FFT passes: the measured prototype of the "DFT as a
+ * matrix product" alternative (a radix-16 DFT is the product of the 16 x 16
+ * DFT matrix with the transform's values; Cooley and Tukey's 4 x 4 split is
+ * the butterfly).  `data` (device, 16-byte aligned) holds `count` transforms
+ * of 16 complex FP64 values, [count][16] interleaved (re, im); each is
+ * replaced in place by (F / 4)^rounds x with F[k][n] = exp(-2 pi i n k / 16),
+ * the values passing through LDS between rounds as between FFT passes.
+ * method 0: one transform per lane, the FFTs' butterfly on the vector
+ * units; method 1: 16 transforms per wave as real 16 x 32 by 32 x 16
+ * products on v_mfma_f64_16x16x4.  Not used by the propagation path.
+ * Asynchronous on `stream`.  Errors: SSFM_EINVAL (method not 0/1, NULL or
+ * misaligned data, count not a non-negative multiple of 64, rounds outside
+ * [0, 2^20]), SSFM_EHIP. */
+int ssfm_dft16_rounds(int method, void* data, int64_t count, int rounds, void* stream);
+
 /* Static description of a status code (never NULL). */
 const char* ssfm_status_string(int status);
 

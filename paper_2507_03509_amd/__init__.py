@@ -23,7 +23,7 @@ __all__ = [
     "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch",
     "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
     "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats", "propagate",
-    "SsfmTuneInfo", "ssfm_plan_autotune", "ssfm_stream_copy",
+    "SsfmTuneInfo", "ssfm_plan_autotune", "ssfm_stream_copy", "ssfm_dft16_rounds",
     "SSFM_OK", "SSFM_EINVAL", "SSFM_ENOMEM", "SSFM_EHIP", "SSFM_EUNSUPPORTED",
 ]
 
@@ -138,6 +138,7 @@ def load_library() -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, VP]
     lib.ssfm_plan_autotune.argtypes = [P, I64, VP, ctypes.POINTER(SsfmTuneInfo)]
     lib.ssfm_stream_copy.argtypes = [VP, VP, I64, VP]
+    lib.ssfm_dft16_rounds.argtypes = [ctypes.c_int, VP, I64, ctypes.c_int, VP]
     lib.ssfm_profile_begin.argtypes = [P]
     lib.ssfm_profile_end.argtypes = [P, ctypes.POINTER(SsfmKernelStats), ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_int)]
@@ -149,7 +150,7 @@ def load_library() -> ctypes.CDLL:
     for name in ("ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info", "ssfm_forward",
                  "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version",
                  "ssfm_profile_begin", "ssfm_profile_end", "ssfm_plan_autotune",
-                 "ssfm_stream_copy"):
+                 "ssfm_stream_copy", "ssfm_dft16_rounds"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -314,6 +315,19 @@ def ssfm_stream_copy(dst, src, stream=None) -> None:
         raise ValueError("dst and src differ in size")
     _check(load_library().ssfm_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes,
                                            _stream_ptr(src, stream)), "ssfm_stream_copy")
+
+
+def ssfm_dft16_rounds(method: int, data, rounds: int, stream=None) -> None:
+    """In place on the device complex128 tensor ``data`` of shape
+    (count, 16), count a multiple of 64: each row becomes (F/4)^rounds x with
+    the 16-point DFT matrix F; method 0 vector butterfly, 1 matrix cores."""
+    if data.dtype != __import__("torch").complex128 or data.dim() != 2 or data.shape[1] != 16:
+        raise ValueError("data must be a complex128 tensor of shape (count, 16)")
+    if not data.is_contiguous():
+        raise ValueError("data must be contiguous")
+    _check(load_library().ssfm_dft16_rounds(int(method), data.data_ptr(), data.shape[0],
+                                            int(rounds), _stream_ptr(data, stream)),
+           "ssfm_dft16_rounds")
 
 
 def ssfm_batch(links, fields, seeds, hip_device: int = 0, stream=None) -> None:
