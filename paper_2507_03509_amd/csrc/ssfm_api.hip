@@ -915,20 +915,21 @@ int ssfm_plan_autotune(ssfm_plan_t plan, int64_t batch, void* stream, ssfm_tune_
       return r == hipSuccess ? cols.col[ssfm::MODE_NL](a, batch, st) : r;
     };
     if ((e = step()) != hipSuccess) break;  // warm-up
-    int reps = 3;
+    int reps = 3, timed = 0;
     float ms = 0.0f;
-    for (int round = 0; round < 2 && e == hipSuccess; ++round) {
+    for (int round = 0; round < 3 && e == hipSuccess; ++round) {
       if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
       for (int r = 0; r < reps && e == hipSuccess; ++r) e = step();
       if (e != hipSuccess || (e = hipEventRecord(e1, st)) != hipSuccess) break;
       if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
       if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      timed = reps;
       // at least ~2 ms of work in the measured round
-      if (ms >= 2.0f) break;
-      reps = (int)std::min<double>(1000.0, std::ceil(reps * 2.0 / std::max(ms, 1e-3f)));
+      if (ms >= 2.0f || reps >= 4000) break;
+      reps = (int)std::min<double>(4000.0, std::ceil(reps * 2.5 / std::max(ms, 1e-3f)));
     }
     if (e != hipSuccess) break;
-    info->us_per_step[idx] = 1e3 * (double)ms / reps;
+    info->us_per_step[idx] = 1e3 * (double)ms / timed;
     if (best_idx < 0 || info->us_per_step[idx] < best) {
       best = info->us_per_step[idx];
       best_idx = idx;
