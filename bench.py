@@ -56,6 +56,9 @@ def parse():
                     help="minimum CPU time of the oracle baseline sample")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="time one forward+adjoint call on the batch (0 to skip)")
+    ap.add_argument("--adjoint-state-gib", type=float, default=-1.0,
+                    help="device memory for the adjoint's kept spans (GiB); -1: all "
+                         "but 8 GiB of the memory free before the call, 0: none")
     ap.add_argument("--dft16", action="store_true",
                     help="time the radix-16 DFT stage prototype: the FFTs' vector "
                          "butterfly against the matrix-core product (one JSON line)")
@@ -513,24 +516,49 @@ def main() -> int:
     adj = None
     if args.adjoint:
         grad = field.clone()
-        plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)  # workspace + warm-up
-        torch.cuda.synchronize()
-        a0 = torch.cuda.Event(enable_timing=True)
-        a1 = torch.cuda.Event(enable_timing=True)
-        a0.record(stream)
-        plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
-        a1.record(stream)
-        torch.cuda.synchronize()
-        ms_adj = a0.elapsed_time(a1)
-        # per-kernel breakdown of one more call (events around every launch)
-        ssfm.ssfm_profile_begin(plan.handle)
-        plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
-        torch.cuda.synchronize()
-        for s_ in ssfm.ssfm_profile_end(plan.handle):
-            log(f"  adjoint call {s_['name']}: {s_['launches']} launches, {s_['total_ms']:.1f} ms, "
-                f"{s_['field_bytes'] / (s_['total_ms'] * 1e-3) / 1e9:.1f} GB/s algorithmic")
-        adj = {"fwd_adjoint_ms": round(ms_adj, 3), "ratio_to_forward": round(ms_adj / ms_per_step, 3)}
-        log(f"forward+adjoint: {ms_adj:.3f} ms ({ms_adj / ms_per_step:.2f}x forward)")
+
+        def time_adjoint(label):
+            plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)  # workspace + warm-up
+            torch.cuda.synchronize()
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            ms = a0.elapsed_time(a1)
+            # per-kernel breakdown of one more call (events around every launch)
+            ssfm.ssfm_profile_begin(plan.handle)
+            plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
+            torch.cuda.synchronize()
+            for s_ in ssfm.ssfm_profile_end(plan.handle):
+                log(f"  adjoint call ({label}) {s_['name']}: {s_['launches']} launches, "
+                    f"{s_['total_ms']:.1f} ms, "
+                    f"{s_['field_bytes'] / (s_['total_ms'] * 1e-3) / 1e9:.1f} GB/s algorithmic")
+            log(f"forward+adjoint ({label}): {ms:.3f} ms ({ms / ms_per_step:.2f}x forward)")
+            return ms
+
+        # reverse sweep rebuilding every span's states from its checkpoint
+        ms_rebuild = time_adjoint("span checkpoints")
+        adj = {"fwd_adjoint_ms": round(ms_rebuild, 3),
+               "ratio_to_forward": round(ms_rebuild / ms_per_step, 3),
+               "rebuild_ms": round(ms_rebuild, 3), "kept_spans": 0}
+        # trailing spans kept: their nonlinear-step inputs stored by the forward
+        if args.adjoint_state_gib != 0:
+            span_bytes = link.steps_per_span * batch * link.n_pol * link.n_samples * 8
+            if args.adjoint_state_gib > 0:
+                budget = int(args.adjoint_state_gib * 2 ** 30)
+            else:
+                budget = max(0, torch.cuda.mem_get_info()[0] - 8 * 2 ** 30)
+            kept = min(link.n_spans, budget // span_bytes)
+            if kept > 0:
+                plan.set_state_memory(kept * span_bytes)
+                ms_kept = time_adjoint(f"{kept} of {link.n_spans} spans kept")
+                plan.set_state_memory(0)
+                adj.update({"fwd_adjoint_ms": round(ms_kept, 3),
+                            "ratio_to_forward": round(ms_kept / ms_per_step, 3),
+                            "kept_spans": int(kept),
+                            "state_gib": round(kept * span_bytes / 2 ** 30, 1)})
         del grad
 
     # ---- one field (batch 1): the latency-bound figure ----------------------
@@ -631,6 +659,7 @@ def main() -> int:
         "rel_err_vs_oracle": rel_err,
         "fwd_adjoint_ms": adj["fwd_adjoint_ms"] if adj else None,
         "fwd_adjoint_ratio": adj["ratio_to_forward"] if adj else None,
+        "fwd_adjoint": adj,
         "pol_sample_steps_per_s": value * p,
         "batch1": single,
         "batch64": b64,

@@ -142,13 +142,30 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
  * through each step (linear: conj(H); nonlinear: g e^{-i phi} +
  * 2 s coef x, s = -Im sum conj(g) y; amplifier: sqrt(G)).  Pullback formulas:
  * chain rule in Wirtinger calculus for y = x exp(i coef sum|x|^2).
- * Workspace: (n_spans + 2) * batch * n_pol * n_samples * 8 bytes, allocated
- * on first use (and grown) and owned by the plan.  Asynchronous like
- * ssfm_forward.  Errors: SSFM_EINVAL (NULL/misaligned pointers, batch < 1),
- * SSFM_EUNSUPPORTED for n_samples < 2^14 (LDS-resident path), SSFM_ENOMEM,
- * SSFM_EHIP. */
+ * Kept spans: with a state budget set (ssfm_plan_set_state_memory), the
+ * forward pass also stores the input x of every nonlinear step of the last
+ * K spans (K = the number of whole spans of steps_per_span * batch * n_pol *
+ * n_samples * 8 bytes that the budget holds, at most n_spans), rounded to
+ * complex64; the reverse sweep of those spans carries the cotangent alone
+ * and takes x from the store (y = x e^{i phi}, phi = coef sum|x|^2).  The
+ * result differs from the reconstructing sweep by rounding only.
+ * Workspace: (n_spans + 2) * batch * n_pol * n_samples * 8 bytes, plus the
+ * kept spans' states, allocated on first use (and grown) and owned by the
+ * plan; if the device refuses the states' allocation, fewer spans are kept.
+ * Asynchronous like ssfm_forward.  Errors: SSFM_EINVAL (NULL/misaligned
+ * pointers, batch < 1), SSFM_EUNSUPPORTED for n_samples < 2^14
+ * (LDS-resident path), SSFM_ENOMEM, SSFM_EHIP. */
 int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
                  int64_t batch, uint64_t seed, void* stream);
+
+/* Device memory, in bytes, that ssfm_adjoint may hold for the kept spans'
+ * nonlinear-step inputs (see ssfm_adjoint); 0 (the default) keeps none.
+ * Trading memory for the reverse sweep's work: a kept span's reverse sweep
+ * moves one field per pass instead of two.  The store is allocated by the
+ * next ssfm_adjoint call that needs it and released by ssfm_plan_destroy,
+ * or here when it exceeds the new budget (after the work using it is done).
+ * Errors: SSFM_EINVAL (NULL plan), SSFM_EHIP. */
+int ssfm_plan_set_state_memory(ssfm_plan_t plan, uint64_t bytes);
 
 /* Independent realisations of different links in one call: entry i (of
  * `count`) propagates the device field fields[i] (complex64

@@ -392,11 +392,20 @@ template <int M, bool PRE = (fft_twiddles<M>::count <= 2)>
 struct lane_twiddles {
   fft_twiddles<M> t;
   __device__ __forceinline__ lane_twiddles(const cd* __restrict__ tw, int j) { t.load(tw, j); }
+  // Hide the values from the optimiser: what a transform computes from them
+  // (the powers of the pass twiddle) is then formed again in the next one
+  // instead of being kept in registers from the earlier transform.
+  __device__ __forceinline__ void opaque() {
+#pragma unroll
+    for (int i = 0; i < fft_twiddles<M>::count; ++i)
+      asm volatile("" : "+v"(t.w[i].re), "+v"(t.w[i].im));
+  }
 };
 template <int M>
 struct lane_twiddles<M, false> {
   const cd* tw;
   __device__ __forceinline__ lane_twiddles(const cd* __restrict__ table, int) : tw(table) {}
+  __device__ __forceinline__ void opaque() {}
 };
 
 template <int M, bool INV, int PAD, bool WAVE, typename L, bool PRE>

@@ -33,9 +33,12 @@ __device__ __forceinline__ col_buf make_col_buf(const float2* base, uint32_t byt
                                             0x00020000),
           lane, step};
 }
-__device__ __forceinline__ cd col_load(const col_buf& b, int r) {
-  const float2 v = __builtin_bit_cast(
+__device__ __forceinline__ float2 col_load_f2(const col_buf& b, int r) {
+  return __builtin_bit_cast(
       float2, __builtin_amdgcn_raw_buffer_load_b64(b.rs, b.lane, (uint32_t)r * b.step, 0));
+}
+__device__ __forceinline__ cd col_load(const col_buf& b, int r) {
+  const float2 v = col_load_f2(b, r);
   return {(double)v.x, (double)v.y};
 }
 __device__ __forceinline__ void col_store(const col_buf& b, int r, cd v) {

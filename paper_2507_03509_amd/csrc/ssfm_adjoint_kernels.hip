@@ -144,6 +144,90 @@ void k3_adj(AdjArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// K3 adjoint with stored states: column tiles of the cotangent alone (the
+// forward pass stored the nonlinear step's input x in the time domain).
+// Lanes: polarisation x C columns x T, as in the forward column pass.
+//   cotangent mixed -> time;  phi = kappa sum_q |x_q|^2;
+//   g' = g e^{-i phi},  s = -Im sum_q conj(g'_q) x_q  (= -Im sum_q conj(g_q) y_q
+//   with y = x e^{i phi});  g_x = g' + 2 s kappa x;  time -> mixed.
+// The per-polarisation powers and s terms are exchanged through the two
+// halves of the LDS tile (FP64); both lanes of a sample form the sums in the
+// same order, so they use the same phase and the same s.
+// ---------------------------------------------------------------------------
+template <int N1, int C, int P>
+__global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k3_adj_stored(AdjStoredArgs a) {
+  constexpr int T = N1 / 16;
+  extern __shared__ __align__(16) unsigned char lds_as[];
+  cd* lds = reinterpret_cast<cd*>(lds_as);
+  const int tid = threadIdx.x;
+  const int p = tid / (C * T);
+  const int rem = tid % (C * T);
+  const int c = rem % C;
+  const int j = rem / C;
+  const int tiles = a.n2 / C;
+  const unsigned G = gridDim.x;
+  const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int64_t b = id / tiles;
+  const int col0 = (int)(id % tiles) * C;
+  const uint32_t tile_bytes = (uint32_t)((P * a.n - col0) * 8);
+  const uint32_t lane_off = (uint32_t)(p * a.n + c + (int64_t)j * a.n2) * 8u;
+  const uint32_t step = (uint32_t)(T * a.n2) * 8u;
+  const col_buf gb = make_col_buf(a.cot + b * P * a.n + col0, tile_bytes, lane_off, step);
+  const col_buf xb = make_col_buf(a.state + b * P * a.n + col0, tile_bytes, lane_off, step);
+  cd reg[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) reg[r] = col_load(gb, r);
+  float2 xs[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) xs[r] = col_load_f2(xb, r);
+  // the pass twiddles' powers are formed in each transform (kept from the
+  // inverse to the forward transform they would hold 60 registers)
+  lane_twiddles<N1> ltw(a.tw1, j);
+  ltw.opaque();
+  cd* mylds = lds + p * (N1 * C) + c;
+  fft<N1, true, false, false>(reg, mylds, C, j, ltw);  // cotangent: mixed -> time
+  constexpr int F = N1 * C;  // one polarisation plane of a half
+  double* pw = reinterpret_cast<double*>(lds_as);      // powers: first half
+  double* sp = pw + P * F;                             // s terms: second half
+  double phi[16];
+  __syncthreads();  // the inverse FFT's LDS reads are done
+  if constexpr (P == 2) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      pw[p * F + (j + T * r) * C + c] =
+          fma((double)xs[r].x, (double)xs[r].x, (double)xs[r].y * (double)xs[r].y);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = (j + T * r) * C + c;
+      phi[r] = a.kappa * (pw[i] + pw[F + i]);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      phi[r] = a.kappa * fma((double)xs[r].x, (double)xs[r].x, (double)xs[r].y * (double)xs[r].y);
+  }
+  for_each_phasor16(phi, [&](int r, cd e) {  // e = e^{i phi}
+    const cd g = cmulc(reg[r], e);
+    reg[r] = g;
+    sp[p * F + (j + T * r) * C + c] = fma(g.im, (double)xs[r].x, -g.re * (double)xs[r].y);
+  });
+  if constexpr (P == 2) __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = (j + T * r) * C + c;
+    const double sr = P == 2 ? sp[i] + sp[F + i] : sp[i];
+    const double w = 2.0 * sr * a.kappa;
+    reg[r] = {fma(w, (double)xs[r].x, reg[r].re), fma(w, (double)xs[r].y, reg[r].im)};
+  }
+  ltw.opaque();
+  fft<N1, false, false, false>(reg, mylds, C, j, ltw);  // time -> mixed
+#pragma unroll
+  for (int r = 0; r < 16; ++r) col_store(gb, r, reg[r]);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 // padded FFT regions of both fields; the nonlinear exchange (2 P N1 C values)
@@ -171,6 +255,24 @@ static hipError_t prepare_k3_adj() {
   return hipSuccess;
 }
 
+template <int N1, int C, int P>
+static hipError_t launch_k3_adj_stored(const AdjStoredArgs& a, int64_t batch, hipStream_t st) {
+  constexpr int T = N1 / 16;
+  const size_t lds = (size_t)P * C * N1 * sizeof(cd);
+  const unsigned blocks = (unsigned)(batch * (a.n2 / C));
+  hipLaunchKernelGGL((k3_adj_stored<N1, C, P>), dim3(blocks), dim3(P * C * T), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int N1, int C, int P>
+static hipError_t prepare_k3_adj_stored() {
+  const size_t lds = (size_t)P * C * N1 * sizeof(cd);
+  if (lds > 65536)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_adj_stored<N1, C, P>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
 // adjoint column tiles: 4 columns (2 at N1 = 512), both fields, FP64 LDS
 // (68 KB per workgroup with the padding)
 template <int N1, int P>
@@ -183,6 +285,12 @@ static void fill_adj(KernelSet& ks) {
   for (hipError_t e : {prepare_k3_adj<N1, C, P, AMODE_FIRST>(), prepare_k3_adj<N1, C, P, AMODE_NL>(),
                        prepare_k3_adj<N1, C, P, AMODE_LAST>()})
     if (e != hipSuccess) ks.prepare = e;
+  // cotangent-only tiles with stored states: the forward column pass's wide
+  // tile (8 columns, 4 at N1 = 512; 64 KB of FP64 LDS)
+  constexpr int CS = N1 == 512 ? 4 : 8;
+  ks.adj_stored = &launch_k3_adj_stored<N1, CS, P>;
+  const hipError_t e = prepare_k3_adj_stored<N1, CS, P>();
+  if (e != hipSuccess) ks.prepare = e;
 }
 
 void select_adjoint_kernels(int n1, int n_pol, KernelSet& ks) {

@@ -114,6 +114,10 @@ struct ssfm_plan_s {
   float2* adj_ckpt = nullptr;
   float2* adj_work = nullptr;
   size_t adj_ckpt_bytes = 0, adj_work_bytes = 0;
+  // the adjoint's stored nonlinear-step inputs (ssfm_plan_set_state_memory)
+  uint64_t state_budget = 0;
+  float2* adj_states = nullptr;
+  size_t adj_states_bytes = 0;
 
   ~ssfm_plan_s() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -122,6 +126,7 @@ struct ssfm_plan_s {
     for (void* p : allocations) (void)hipFree(p);
     if (adj_ckpt) (void)hipFree(adj_ckpt);
     if (adj_work) (void)hipFree(adj_work);
+    if (adj_states) (void)hipFree(adj_states);
   }
 };
 
@@ -335,9 +340,13 @@ bool use_graphs(const ssfm_plan_s* p) {
   return !(env && strcmp(env, "0") == 0);
 }
 
+// states (four-step path): for spans s >= state_span0, the input of each
+// nonlinear step i is stored at states + ((s - state_span0) steps + i) slice,
+// slice = batch * n_pol * n elements.
 int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uint64_t real0,
                 int s0, int s1, hipStream_t st, float2* ckpt = nullptr,
-                const uint64_t* seeds = nullptr) {
+                const uint64_t* seeds = nullptr, float2* states = nullptr,
+                int state_span0 = 0) {
   const ssfm::KernelSet& ks = p->ks;
   hipError_t e;
   if (s0 == s1) return SSFM_OK;
@@ -400,11 +409,18 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
       if (i < p->steps) {
         mode = ssfm::MODE_NL;
         a.kappa = p->kappa[(size_t)i];
+        if (states && s >= state_span0) {
+          mode = ssfm::MODE_NL_STORE;
+          a.states = states + ((size_t)(s - state_span0) * p->steps + (size_t)i) *
+                                  ((size_t)batch * p->n_pol * p->n);
+        }
       } else {
         mode = s + 1 < s1 ? ssfm::MODE_EDFA : ssfm::MODE_LAST;
         a.ckpt = ckpt ? ckpt + (size_t)s * batch * p->n_pol * p->n : nullptr;
       }
-      if ((e = launch(p, KIND_COL, field_bytes, st,
+      // a stored nonlinear-step input is one more write of the field
+      const double bytes = mode == ssfm::MODE_NL_STORE ? 1.5 * field_bytes : field_bytes;
+      if ((e = launch(p, KIND_COL, bytes, st,
                       [&] { return cols.col[mode](a, batch, st); })) != hipSuccess)
         return api_fail_hip(e, "k3 launch");
     }
@@ -664,13 +680,32 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
     plan->adj_ckpt_bytes = ckpt_bytes;
     plan->adj_work_bytes = work_bytes;
   }
+  // trailing spans whose nonlinear-step inputs the forward pass keeps, as
+  // many as the plan's state budget holds (grown on demand; an allocation
+  // the device refuses lowers the count)
+  const size_t span_state_bytes = (size_t)plan->steps * slice * sizeof(float2);
+  int kept = (int)std::min<uint64_t>((uint64_t)plan->spans, plan->state_budget / span_state_bytes);
+  if ((size_t)kept * span_state_bytes > plan->adj_states_bytes) {
+    if (plan->adj_states) (void)hipFree(plan->adj_states);
+    plan->adj_states = nullptr;
+    plan->adj_states_bytes = 0;
+    while (kept > 0 && hipMalloc(&plan->adj_states, (size_t)kept * span_state_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      plan->adj_states = nullptr;
+      --kept;
+    }
+    if (kept > 0) plan->adj_states_bytes = (size_t)kept * span_state_bytes;
+  }
+  const int kept_span0 = plan->spans - kept;
   float2* work = plan->adj_work;
   float2* cot = work + slice;
-  // forward pass on a copy of the input, keeping the span-end states
+  // forward pass on a copy of the input, keeping the span-end states (and the
+  // nonlinear-step inputs of the kept spans)
   if ((e = hipMemcpyAsync(work, field_in, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
     return api_fail_hip(e, "hipMemcpyAsync (adjoint input)");
-  rc = run_forward(plan, work, batch, seed, 0, 0, plan->spans, st, plan->adj_ckpt);
+  rc = run_forward(plan, work, batch, seed, 0, 0, plan->spans, st, plan->adj_ckpt, nullptr,
+                   kept > 0 ? plan->adj_states : nullptr, kept_span0);
   if (rc != SSFM_OK) return rc;
   if ((e = hipMemcpyAsync(cot, grad, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
@@ -698,7 +733,47 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
   aa.n = plan->n;
   aa.batch = batch;
   aa.gspan = plan->gspan;
-  for (int s = plan->spans - 1; s >= 0; --s) {
+  // cotangent-only reverse sweep of a kept span: the forward column pass's
+  // transforms, the conjugate row pass and the stored-state pullback
+  const Shape4 shape1 = pick_shape(plan, batch);
+  const int64_t rows1 = batch * plan->n_pol * ks.n1;
+  const double bytes1 = 2.0 * (double)slice * sizeof(float2);
+  ssfm::RowArgs rc1 = ra;
+  rc1.field = cot;
+  ssfm::ColArgs ca{};
+  ca.field = cot;
+  ca.tw1 = plan->tw1;
+  ca.n2 = ks.n2;
+  ca.n = plan->n;
+  ca.gspan = plan->gspan;
+  ca.sigma_h = 0.0;  // the pullback of the amplifier is the gain alone
+  ssfm::AdjStoredArgs sa{};
+  sa.cot = cot;
+  sa.tw1 = plan->tw1;
+  sa.n2 = ks.n2;
+  sa.n = plan->n;
+  for (int s = plan->spans - 1; s >= kept_span0; --s) {
+    if ((e = launch(plan, KIND_COL, bytes1, st,
+                    [&] { return shape1.cols->col[ssfm::MODE_FIRST](ca, batch, st); })) != hipSuccess)
+      return api_fail_hip(e, "k3 launch (adjoint)");
+    for (int i = plan->steps; i >= 0; --i) {
+      rc1.H = (i == 0 || i == plan->steps) ? plan->h_half : plan->h_full;
+      if ((e = launch(plan, KIND_ROW, bytes1, st, [&] { return shape1.row(rc1, rows1, st); })) !=
+          hipSuccess)
+        return api_fail_hip(e, "k2 launch (adjoint)");
+      if (i > 0) {
+        sa.kappa = plan->kappa[(size_t)(i - 1)];
+        sa.state = plan->adj_states + ((size_t)(s - kept_span0) * plan->steps + (size_t)(i - 1)) * slice;
+        if ((e = launch(plan, KIND_ADJ, 1.5 * bytes1, st,
+                        [&] { return ks.adj_stored(sa, batch, st); })) != hipSuccess)
+          return api_fail_hip(e, "k3_adj_stored launch");
+      }
+    }
+    if ((e = launch(plan, KIND_COL, bytes1, st,
+                    [&] { return shape1.cols->col[ssfm::MODE_LAST](ca, batch, st); })) != hipSuccess)
+      return api_fail_hip(e, "k3 launch (adjoint)");
+  }
+  for (int s = kept_span0 - 1; s >= 0; --s) {
     aa.ckpt = plan->adj_ckpt + (size_t)s * slice;
     if ((e = launch(plan, KIND_ADJ, row_bytes, st,
                     [&] { return ks.adj[ssfm::AMODE_FIRST](aa, st); })) != hipSuccess)
@@ -722,6 +797,20 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
   if ((e = hipMemcpyAsync(grad, cot, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
     return api_fail_hip(e, "hipMemcpyAsync (gradient)");
+  return SSFM_OK;
+}
+
+int ssfm_plan_set_state_memory(ssfm_plan_t plan, uint64_t bytes) {
+  ssfm::api_clear_error();
+  if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
+  plan->state_budget = bytes;
+  if (plan->adj_states && plan->adj_states_bytes > bytes) {
+    DeviceGuard guard(plan->device);
+    if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
+    (void)hipFree(plan->adj_states);  // waits for work still using it
+    plan->adj_states = nullptr;
+    plan->adj_states_bytes = 0;
+  }
   return SSFM_OK;
 }
 

@@ -9,10 +9,12 @@
 namespace ssfm {
 
 // column-pass variants
-enum { MODE_FIRST = 0,   // time -> mixed domain (start of the link)
-       MODE_NL = 1,      // mixed -> time, nonlinear phase, time -> mixed
-       MODE_EDFA = 2,    // mixed -> time, amplifier + ASE, time -> mixed
-       MODE_LAST = 3 };  // mixed -> time, amplifier + ASE (end of the link)
+enum { MODE_FIRST = 0,      // time -> mixed domain (start of the link)
+       MODE_NL = 1,         // mixed -> time, nonlinear phase, time -> mixed
+       MODE_EDFA = 2,       // mixed -> time, amplifier + ASE, time -> mixed
+       MODE_LAST = 3,       // mixed -> time, amplifier + ASE (end of the link)
+       MODE_NL_STORE = 4,   // MODE_NL, also storing the nonlinear step's input
+       N_MODES = 5 };
 
 struct RowArgs {
   float2* field;
@@ -40,6 +42,8 @@ struct ColArgs {
                      // field is stored here ([batch][pol][n]), else unused
   const uint64_t* seeds;  // if set, realisation b's noise key is
                           // (seeds[b], span), else (seed, (realization0 + b) 2^16 + span)
+  float2* states;    // MODE_NL_STORE: the time-domain field entering the
+                     // nonlinear step, rounded to complex64, [batch][pol][n]
 };
 
 // adjoint column-pass variants (state = reconstructed forward field,
@@ -75,13 +79,25 @@ struct LdsArgs {
   const uint64_t* seeds;  // as ColArgs::seeds
 };
 
+// adjoint column pass over the cotangent alone, with the forward state read
+// from the nonlinear-step inputs stored by MODE_NL_STORE
+struct AdjStoredArgs {
+  float2* cot;         // cotangent [batch][pol][n], mixed domain in and out
+  const float2* state; // the step's stored nonlinear-step input, time domain
+  const cd* tw1;
+  int n2;
+  int64_t n;
+  double kappa;
+};
+
 using RowLaunch = hipError_t (*)(const RowArgs&, int64_t, hipStream_t);
 using ColLaunch = hipError_t (*)(const ColArgs&, int64_t, hipStream_t);
 using LdsLaunch = hipError_t (*)(const LdsArgs&, int64_t, hipStream_t);
 using AdjLaunch = hipError_t (*)(const AdjArgs&, hipStream_t);
+using AdjStoredLaunch = hipError_t (*)(const AdjStoredArgs&, int64_t, hipStream_t);
 
 struct FourStepKernels {
-  ColLaunch col[4] = {nullptr, nullptr, nullptr, nullptr};
+  ColLaunch col[N_MODES] = {};
   int columns = 0;
   hipError_t prepare_status = hipSuccess;
 };
@@ -96,6 +112,7 @@ struct KernelSet {
   FourStepKernels narrow, mid, wide;
   AdjLaunch adj[3] = {nullptr, nullptr, nullptr};
   int adj_columns = 0;
+  AdjStoredLaunch adj_stored = nullptr;
   hipError_t prepare = hipSuccess;
 };
 

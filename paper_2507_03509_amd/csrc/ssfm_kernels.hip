@@ -124,7 +124,13 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
   if constexpr (MODE != MODE_FIRST) {
     // mixed (k1, n2) domain -> time: inverse column FFT
     fft<N1, true, false, false>(reg, mylds, C, j, ltw);
-    if constexpr (MODE == MODE_NL) {
+    if constexpr (MODE == MODE_NL_STORE) {
+      // the nonlinear step's input, kept for the adjoint's reverse sweep
+      const col_buf sb = make_col_buf(a.states + b * P * a.n + col0, tile_bytes, lane_off, step);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) col_store(sb, r, reg[r]);
+    }
+    if constexpr (MODE == MODE_NL || MODE == MODE_NL_STORE) {
       if constexpr (P == 2) {
         // exchange |a_p|^2 with the lane of the other polarisation (the sum
         // is formed x + y on both lanes, so both rotate by the same phase)
@@ -365,11 +371,13 @@ static void fill_k3(FourStepKernels& k) {
   k.col[MODE_NL] = &launch_k3<N1, C, P, MODE_NL, L>;
   k.col[MODE_EDFA] = &launch_k3<N1, C, P, MODE_EDFA, L>;
   k.col[MODE_LAST] = &launch_k3<N1, C, P, MODE_LAST, L>;
+  k.col[MODE_NL_STORE] = &launch_k3<N1, C, P, MODE_NL_STORE, L>;
   k.columns = C;
   k.prepare_status = prepare_k3_one<N1, C, P, MODE_FIRST, L>();
   if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_NL, L>();
   if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_EDFA, L>();
   if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_LAST, L>();
+  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_NL_STORE, L>();
 }
 
 template <int N1, int P>

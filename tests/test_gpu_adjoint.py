@@ -35,11 +35,13 @@ def link(n_pol, n, spans, steps, **kw):
     return Link(**base)
 
 
-def gpu_adjoint(ssfm, x, g, ln, seed):
+def gpu_adjoint(ssfm, x, g, ln, seed, state_bytes=0):
     xt = torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).cuda()
     gt = torch.from_numpy(np.ascontiguousarray(g, dtype=np.complex64)).cuda()
     plan = ssfm.Plan(ln)
     try:
+        if state_bytes:
+            plan.set_state_memory(state_bytes)
         plan.adjoint(xt, gt, seed=seed)
         torch.cuda.synchronize()
     finally:
@@ -107,14 +109,69 @@ def test_adjoint_rejects_lds_path(ssfm):
     plan.close()
 
 
+@pytest.mark.parametrize("kept", [False, True])
 @pytest.mark.parametrize("n,n_pol", [(1 << 14, 2), (1 << 15, 1)])
-def test_adjoint_large_nonlinear_phase(ssfm, n, n_pol):
+def test_adjoint_large_nonlinear_phase(ssfm, n, n_pol, kept):
     # 18 dBm over 20 km steps: per-step phases of several rad on most samples
-    print(f"case n={n} n_pol={n_pol}", flush=True)
+    print(f"case n={n} n_pol={n_pol} kept={kept}", flush=True)
     rng = np.random.default_rng(n + n_pol)
     ln = link(n_pol, n, spans=1, steps=4)
     x = dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 18.0)
     g = dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 0.0)
-    got, _ = gpu_adjoint(ssfm, x[None], g[None], ln, seed=3)
+    budget = 4 * n_pol * n * 8 if kept else 0
+    got, _ = gpu_adjoint(ssfm, x[None], g[None], ln, seed=3, state_bytes=budget)
     want = oracle.adjoint(x, g, ln, seed=3)
     assert rel(got[0], want) < 1e-5, rel(got[0], want)
+
+
+# ---------------------------------------------------------------------------
+# kept spans: the forward pass stores the nonlinear-step inputs of the last
+# K spans (K set by the state budget) and their reverse sweep carries the
+# cotangent alone
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,n_pol,spans,kept", [(1 << 16, 2, 3, 3), (1 << 16, 2, 3, 1),
+                                                (1 << 14, 1, 2, 2), (1 << 15, 2, 2, 1),
+                                                (1 << 18, 2, 2, 2)])
+def test_adjoint_kept_spans_match_oracle(ssfm, n, n_pol, spans, kept):
+    print(f"case n={n} n_pol={n_pol} spans={spans} kept={kept}", flush=True)
+    rng = np.random.default_rng(3 * n + n_pol + spans)
+    steps, b = 5, 2
+    ln = link(n_pol, n, spans=spans, steps=steps)
+    x = np.stack([dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 6.0) for _ in range(b)])
+    g = np.stack([dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 0.0) for _ in range(b)])
+    per_span = steps * b * n_pol * n * 8
+    got, x_after = gpu_adjoint(ssfm, x, g, ln, seed=9, state_bytes=kept * per_span + per_span // 2)
+    assert np.array_equal(x_after, x.astype(np.complex64))
+    rebuilt, _ = gpu_adjoint(ssfm, x, g, ln, seed=9)
+    for r in range(b):
+        want = oracle.adjoint(x[r], g[r], ln, seed=9, realization=r)
+        assert rel(got[r], want) < 1e-5, (r, rel(got[r], want))
+        assert rel(got[r], rebuilt[r]) < 5e-6, (r, rel(got[r], rebuilt[r]))
+
+
+def test_adjoint_state_budget_reuse_and_release(ssfm):
+    # the store is kept by the plan across calls; a zero budget releases it
+    # and the next call is the reconstructing sweep again, bit for bit
+    n, steps = 1 << 15, 4
+    ln = link(2, n, spans=2, steps=steps)
+    rng = np.random.default_rng(41)
+    x = torch.from_numpy(dual_pol_field(rng, 2, n, 2, 64e9, 0.1, 6.0).astype(np.complex64))[None].cuda()
+    g0 = torch.from_numpy(dual_pol_field(rng, 2, n, 2, 64e9, 0.1, 0.0).astype(np.complex64))[None].cuda()
+    plan = ssfm.Plan(ln)
+    try:
+        plain = plan.adjoint(x, g0.clone())
+        plan.set_state_memory(2 * steps * 2 * n * 8)
+        kept1 = plan.adjoint(x, g0.clone())
+        kept2 = plan.adjoint(x, g0.clone())
+        plan.set_state_memory(0)
+        again = plan.adjoint(x, g0.clone())
+        torch.cuda.synchronize()
+        assert torch.equal(kept1, kept2)
+        assert torch.equal(plain, again)
+        assert not torch.equal(plain, kept1)  # a different rounding path
+        a = plain.cpu().numpy().astype(np.complex128)
+        k = kept1.cpu().numpy().astype(np.complex128)
+        assert rel(k, a) < 5e-6
+    finally:
+        plan.close()
