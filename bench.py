@@ -602,6 +602,29 @@ def main() -> int:
                "us_per_split_step": round(ms64 * 1e3 / total_steps, 3),
                "sample_steps_per_s": 64 * n * total_steps / (ms64 / 1e3)}
         log(f"batch 64: {ms64:.3f} ms/call, {b64['sample_steps_per_s']:.4e} sample-steps/s")
+        # forward+adjoint at this batch with the nonlinear-step inputs of as
+        # many spans kept as the free memory holds (every span, normally)
+        if args.adjoint and args.adjoint_state_gib != 0:
+            span64 = link.steps_per_span * 64 * link.n_pol * link.n_samples * 8
+            free = max(0, torch.cuda.mem_get_info()[0] - 8 * 2 ** 30)
+            kept64 = min(link.n_spans, free // span64)
+            if kept64 > 0:
+                g64 = f64.clone()
+                plan.set_state_memory(kept64 * span64)
+                plan.adjoint(f64, g64, seed=w.ase_seed, stream=stream)  # store + warm-up
+                torch.cuda.synchronize()
+                e0.record(stream)
+                plan.adjoint(f64, g64, seed=w.ase_seed, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms64a = e0.elapsed_time(e1)
+                plan.set_state_memory(0)
+                b64.update({"fwd_adjoint_ms": round(ms64a, 3),
+                            "fwd_adjoint_ratio": round(ms64a / ms64, 3),
+                            "kept_spans": int(kept64)})
+                log(f"batch 64 forward+adjoint, {kept64} of {link.n_spans} spans kept: "
+                    f"{ms64a:.3f} ms ({ms64a / ms64:.2f}x forward)")
+                del g64
         del f64
 
     # ---- achievable bandwidth: this library's plain copy kernel on the
