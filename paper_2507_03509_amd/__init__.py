@@ -24,7 +24,7 @@ __all__ = [
     "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
     "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats", "propagate",
     "SsfmTuneInfo", "ssfm_plan_autotune", "ssfm_stream_copy", "ssfm_dft16_rounds",
-    "ssfm_plan_set_state_memory",
+    "ssfm_plan_set_state_memory", "ssfm_plan_set_forward_streams",
     "SSFM_OK", "SSFM_EINVAL", "SSFM_ENOMEM", "SSFM_EHIP", "SSFM_EUNSUPPORTED",
 ]
 
@@ -136,6 +136,7 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_forward_spans.argtypes = [P, VP, I64, U64, U64, I32, I32, VP]
     lib.ssfm_adjoint.argtypes = [P, VP, VP, I64, U64, VP]
     lib.ssfm_plan_set_state_memory.argtypes = [P, U64]
+    lib.ssfm_plan_set_forward_streams.argtypes = [P, I32]
     lib.ssfm_batch.argtypes = [ctypes.POINTER(SsfmLink), ctypes.POINTER(ctypes.c_void_p), I64,
                                ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, VP]
     lib.ssfm_plan_autotune.argtypes = [P, I64, VP, ctypes.POINTER(SsfmTuneInfo)]
@@ -152,7 +153,8 @@ def load_library() -> ctypes.CDLL:
     for name in ("ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info", "ssfm_forward",
                  "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version",
                  "ssfm_profile_begin", "ssfm_profile_end", "ssfm_plan_autotune",
-                 "ssfm_stream_copy", "ssfm_dft16_rounds", "ssfm_plan_set_state_memory"):
+                 "ssfm_stream_copy", "ssfm_dft16_rounds", "ssfm_plan_set_state_memory",
+                 "ssfm_plan_set_forward_streams"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -301,6 +303,12 @@ def ssfm_plan_set_state_memory(plan: int, nbytes: int) -> None:
            "ssfm_plan_set_state_memory")
 
 
+def ssfm_plan_set_forward_streams(plan: int, streams: int) -> None:
+    """Concurrent sub-batches of a four-step call: 0 automatic, 1 or 2."""
+    _check(load_library().ssfm_plan_set_forward_streams(plan, int(streams)),
+           "ssfm_plan_set_forward_streams")
+
+
 def ssfm_plan_autotune(plan: int, batch: int, stream=None) -> dict:
     """Measure the four-step launch shapes for ``batch`` and record the
     fastest in the plan (see include/ssfm.h)."""
@@ -378,6 +386,10 @@ class Plan:
     def autotune(self, batch: int, stream=None) -> dict:
         """Choose this plan's launch shape for ``batch`` by measurement."""
         return ssfm_plan_autotune(self.handle, batch, stream)
+
+    def set_forward_streams(self, streams: int) -> None:
+        """Concurrent sub-batches of a four-step call: 0 automatic, 1 or 2."""
+        ssfm_plan_set_forward_streams(self.handle, streams)
 
     def set_state_memory(self, nbytes: int) -> None:
         """Budget for the adjoint's stored nonlinear-step inputs (bytes)."""

@@ -118,6 +118,9 @@ struct ssfm_plan_s {
   uint64_t state_budget = 0;
   float2* adj_states = nullptr;
   size_t adj_states_bytes = 0;
+  // concurrent sub-batches of a four-step call: 0 automatic, 1 or 2
+  // (ssfm_plan_set_forward_streams)
+  int forward_streams = 0;
 
   ~ssfm_plan_s() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -516,6 +519,166 @@ int cached_plan(const ssfm_link& key, int device, ssfm_plan_t* out) {
 }
 }  // namespace
 
+namespace {
+
+// Sub-batches a four-step call runs concurrently: two when each half still
+// gives at least 2048 wide column tiles, else one; the plan's setting
+// (ssfm_plan_set_forward_streams) overrides.  Two sub-batches on two streams
+// fill the tail of each pass and the gap between dependent launches with the
+// other sub-batch's work.
+int forward_parts(const ssfm_plan_s* p, int64_t batch) {
+  if (p->ks.path != 2 || batch < 2) return 1;
+  if (p->forward_streams == 1 || p->forward_streams == 2) return p->forward_streams;
+  const int64_t tiles = (int64_t)p->ks.n2 / p->ks.wide.columns;
+  return (batch / 2) * tiles >= 2048 ? 2 : 1;
+}
+
+// Run part(h, stream) for h = 0, 1 on two worker streams forked from st and
+// joined back into it (also after an error, so that no work is left
+// unordered).
+template <typename F>
+int run_split(ssfm_plan_s* p, hipStream_t st, F&& part) {
+  hipStream_t ws[kBatchStreams];
+  int rc = batch_streams(p->device, ws);
+  if (rc != SSFM_OK) return rc;
+  hipEvent_t ev[3] = {};
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], st);  // fork
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ws[k], ev[2], 0);
+  if (e != hipSuccess) {
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+    return api_fail_hip(e, "sub-batch fork");
+  }
+  for (int h = 0; h < 2 && rc == SSFM_OK; ++h) rc = part(h, ws[h]);
+  hipError_t ej = hipSuccess;
+  for (int k = 0; k < 2; ++k) {
+    if (ej == hipSuccess) ej = hipEventRecord(ev[k], ws[k]);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(st, ev[k], 0);
+  }
+  for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+  if (rc != SSFM_OK) return rc;
+  if (ej != hipSuccess) return api_fail_hip(ej, "sub-batch join");
+  return SSFM_OK;
+}
+
+// The adjoint of `batch` realisations (noise indices real0 + b) on stream st,
+// with the workspace regions of this (sub-)batch: work [2 batch] fields,
+// ckpt [spans][batch], states [kept][steps][batch] (kept trailing spans).
+int run_adjoint(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t batch, uint64_t seed,
+                uint64_t real0, hipStream_t st, float2* work, float2* ckpt, float2* states,
+                int kept) {
+  const ssfm::KernelSet& ks = plan->ks;
+  const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
+  const int kept_span0 = plan->spans - kept;
+  float2* cot = work + slice;
+  hipError_t e;
+  int rc;
+  // forward pass on a copy of the input, keeping the span-end states (and the
+  // nonlinear-step inputs of the kept spans)
+  if ((e = hipMemcpyAsync(work, field_in, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return api_fail_hip(e, "hipMemcpyAsync (adjoint input)");
+  rc = run_forward(plan, work, batch, seed, real0, 0, plan->spans, st, ckpt, nullptr,
+                   kept > 0 ? states : nullptr, kept_span0);
+  if (rc != SSFM_OK) return rc;
+  if ((e = hipMemcpyAsync(cot, grad, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return api_fail_hip(e, "hipMemcpyAsync (cotangent)");
+
+  // reverse sweep: state and cotangent together, span by span
+  const int64_t batch2 = 2 * batch;
+  const ssfm::RowLaunch row = pick_shape(plan, batch2).row;
+  const int64_t rows = batch2 * plan->n_pol * ks.n1;
+  const double row_bytes = 2.0 * (double)batch2 * plan->n_pol * (double)plan->n * sizeof(float2);
+  int log2_n2 = 0;
+  while ((1 << log2_n2) < ks.n2) ++log2_n2;
+  ssfm::RowArgs ra{};
+  ra.field = work;
+  ra.tw = plan->tw2;
+  ra.twA = plan->twA;
+  ra.twB = plan->twB;
+  ra.n1 = ks.n1;
+  ra.log2_n2 = log2_n2;
+  ra.conj_h = 1;
+  ssfm::AdjArgs aa{};
+  aa.work = work;
+  aa.tw1 = plan->tw1;
+  aa.n2 = ks.n2;
+  aa.n = plan->n;
+  aa.batch = batch;
+  aa.gspan = plan->gspan;
+  // cotangent-only reverse sweep of a kept span: the forward column pass's
+  // transforms, the conjugate row pass and the stored-state pullback
+  const Shape4 shape1 = pick_shape(plan, batch);
+  const int64_t rows1 = batch * plan->n_pol * ks.n1;
+  const double bytes1 = 2.0 * (double)slice * sizeof(float2);
+  ssfm::RowArgs rc1 = ra;
+  rc1.field = cot;
+  ssfm::ColArgs ca{};
+  ca.field = cot;
+  ca.tw1 = plan->tw1;
+  ca.n2 = ks.n2;
+  ca.n = plan->n;
+  ca.gspan = plan->gspan;
+  ca.sigma_h = 0.0;  // the pullback of the amplifier is the gain alone
+  ssfm::AdjStoredArgs sa{};
+  sa.cot = cot;
+  sa.tw1 = plan->tw1;
+  sa.n2 = ks.n2;
+  sa.n = plan->n;
+  for (int s = plan->spans - 1; s >= kept_span0; --s) {
+    if ((e = launch(plan, KIND_COL, bytes1, st,
+                    [&] { return shape1.cols->col[ssfm::MODE_FIRST](ca, batch, st); })) != hipSuccess)
+      return api_fail_hip(e, "k3 launch (adjoint)");
+    for (int i = plan->steps; i >= 0; --i) {
+      rc1.H = (i == 0 || i == plan->steps) ? plan->h_half : plan->h_full;
+      if ((e = launch(plan, KIND_ROW, bytes1, st, [&] { return shape1.row(rc1, rows1, st); })) !=
+          hipSuccess)
+        return api_fail_hip(e, "k2 launch (adjoint)");
+      if (i > 0) {
+        sa.kappa = plan->kappa[(size_t)(i - 1)];
+        sa.state = states + ((size_t)(s - kept_span0) * plan->steps + (size_t)(i - 1)) * slice;
+        if ((e = launch(plan, KIND_ADJ, 1.5 * bytes1, st,
+                        [&] { return ks.adj_stored(sa, batch, st); })) != hipSuccess)
+          return api_fail_hip(e, "k3_adj_stored launch");
+      }
+    }
+    if ((e = launch(plan, KIND_COL, bytes1, st,
+                    [&] { return shape1.cols->col[ssfm::MODE_LAST](ca, batch, st); })) != hipSuccess)
+      return api_fail_hip(e, "k3 launch (adjoint)");
+  }
+  for (int s = kept_span0 - 1; s >= 0; --s) {
+    aa.ckpt = ckpt + (size_t)s * slice;
+    if ((e = launch(plan, KIND_ADJ, row_bytes, st,
+                    [&] { return ks.adj[ssfm::AMODE_FIRST](aa, st); })) != hipSuccess)
+      return api_fail_hip(e, "k3_adj launch");
+    for (int i = plan->steps; i >= 0; --i) {
+      ra.H = (i == 0 || i == plan->steps) ? plan->h_half : plan->h_full;
+      if ((e = launch(plan, KIND_ROW, row_bytes, st, [&] { return row(ra, rows, st); })) !=
+          hipSuccess)
+        return api_fail_hip(e, "k2 launch");
+      if (i > 0) {
+        aa.kappa = plan->kappa[(size_t)(i - 1)];
+        if ((e = launch(plan, KIND_ADJ, row_bytes, st,
+                        [&] { return ks.adj[ssfm::AMODE_NL](aa, st); })) != hipSuccess)
+          return api_fail_hip(e, "k3_adj launch");
+      }
+    }
+    if ((e = launch(plan, KIND_ADJ, row_bytes, st,
+                    [&] { return ks.adj[ssfm::AMODE_LAST](aa, st); })) != hipSuccess)
+      return api_fail_hip(e, "k3_adj launch");
+  }
+  if ((e = hipMemcpyAsync(grad, cot, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return api_fail_hip(e, "hipMemcpyAsync (gradient)");
+  return SSFM_OK;
+}
+
+
+}  // namespace
+
 extern "C" {
 
 int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out) {
@@ -588,6 +751,18 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch, uint64_t se
   DeviceGuard guard(plan->device);
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (forward_parts(plan, batch) > 1) {
+    // two sub-batches on worker streams (no graph replay: at such batches
+    // the launches are long against their issue cost)
+    const int64_t b0 = batch / 2;
+    float2* f = static_cast<float2*>(field);
+    const size_t o = (size_t)b0 * plan->n_pol * plan->n;
+    return run_split(plan, st, [&](int h, hipStream_t ws) {
+      return h == 0 ? run_forward(plan, f, b0, seed, realization0, span_begin, span_end, ws)
+                    : run_forward(plan, f + o, batch - b0, seed, realization0 + (uint64_t)b0,
+                                  span_begin, span_end, ws);
+    });
+  }
   if (!use_graphs(plan))
     return run_forward(plan, static_cast<float2*>(field), batch, seed, realization0, span_begin,
                        span_end, st);
@@ -660,11 +835,9 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
   DeviceGuard guard(plan->device);
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const ssfm::KernelSet& ks = plan->ks;
   const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
   const size_t ckpt_bytes = (size_t)plan->spans * slice * sizeof(float2);
   const size_t work_bytes = 2 * slice * sizeof(float2);
-  hipError_t e;
   if (ckpt_bytes > plan->adj_ckpt_bytes || work_bytes > plan->adj_work_bytes) {
     // grow the workspace (hipFree waits for work still using the old one)
     if (plan->adj_ckpt) (void)hipFree(plan->adj_ckpt);
@@ -696,107 +869,31 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
     }
     if (kept > 0) plan->adj_states_bytes = (size_t)kept * span_state_bytes;
   }
-  const int kept_span0 = plan->spans - kept;
-  float2* work = plan->adj_work;
-  float2* cot = work + slice;
-  // forward pass on a copy of the input, keeping the span-end states (and the
-  // nonlinear-step inputs of the kept spans)
-  if ((e = hipMemcpyAsync(work, field_in, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
-      hipSuccess)
-    return api_fail_hip(e, "hipMemcpyAsync (adjoint input)");
-  rc = run_forward(plan, work, batch, seed, 0, 0, plan->spans, st, plan->adj_ckpt, nullptr,
-                   kept > 0 ? plan->adj_states : nullptr, kept_span0);
-  if (rc != SSFM_OK) return rc;
-  if ((e = hipMemcpyAsync(cot, grad, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
-      hipSuccess)
-    return api_fail_hip(e, "hipMemcpyAsync (cotangent)");
+  // two concurrent sub-batches (as a forward call of this batch would run)
+  // on carved halves of the workspace, else one
+  if (forward_parts(plan, batch) == 1)
+    return run_adjoint(plan, field_in, grad, batch, seed, 0, st, plan->adj_work, plan->adj_ckpt,
+                       plan->adj_states, kept);
+  const int64_t b0 = batch / 2;
+  const size_t elems = (size_t)plan->n_pol * plan->n;
+  const int64_t sub[2] = {b0, batch - b0};
+  const int64_t off[2] = {0, b0};
+  return run_split(plan, st, [&](int h, hipStream_t ws) {
+    const size_t o = (size_t)off[h] * elems;
+    return run_adjoint(plan, static_cast<const float2*>(field_in) + o, static_cast<float2*>(grad) + o,
+                       sub[h], seed, (uint64_t)off[h], ws, plan->adj_work + 2 * o,
+                       plan->adj_ckpt + (size_t)plan->spans * o,
+                       plan->adj_states ? plan->adj_states + (size_t)kept * plan->steps * o : nullptr,
+                       kept);
+  });
+}
 
-  // reverse sweep: state and cotangent together, span by span
-  const int64_t batch2 = 2 * batch;
-  const ssfm::RowLaunch row = pick_shape(plan, batch2).row;
-  const int64_t rows = batch2 * plan->n_pol * ks.n1;
-  const double row_bytes = 2.0 * (double)batch2 * plan->n_pol * (double)plan->n * sizeof(float2);
-  int log2_n2 = 0;
-  while ((1 << log2_n2) < ks.n2) ++log2_n2;
-  ssfm::RowArgs ra{};
-  ra.field = work;
-  ra.tw = plan->tw2;
-  ra.twA = plan->twA;
-  ra.twB = plan->twB;
-  ra.n1 = ks.n1;
-  ra.log2_n2 = log2_n2;
-  ra.conj_h = 1;
-  ssfm::AdjArgs aa{};
-  aa.work = work;
-  aa.tw1 = plan->tw1;
-  aa.n2 = ks.n2;
-  aa.n = plan->n;
-  aa.batch = batch;
-  aa.gspan = plan->gspan;
-  // cotangent-only reverse sweep of a kept span: the forward column pass's
-  // transforms, the conjugate row pass and the stored-state pullback
-  const Shape4 shape1 = pick_shape(plan, batch);
-  const int64_t rows1 = batch * plan->n_pol * ks.n1;
-  const double bytes1 = 2.0 * (double)slice * sizeof(float2);
-  ssfm::RowArgs rc1 = ra;
-  rc1.field = cot;
-  ssfm::ColArgs ca{};
-  ca.field = cot;
-  ca.tw1 = plan->tw1;
-  ca.n2 = ks.n2;
-  ca.n = plan->n;
-  ca.gspan = plan->gspan;
-  ca.sigma_h = 0.0;  // the pullback of the amplifier is the gain alone
-  ssfm::AdjStoredArgs sa{};
-  sa.cot = cot;
-  sa.tw1 = plan->tw1;
-  sa.n2 = ks.n2;
-  sa.n = plan->n;
-  for (int s = plan->spans - 1; s >= kept_span0; --s) {
-    if ((e = launch(plan, KIND_COL, bytes1, st,
-                    [&] { return shape1.cols->col[ssfm::MODE_FIRST](ca, batch, st); })) != hipSuccess)
-      return api_fail_hip(e, "k3 launch (adjoint)");
-    for (int i = plan->steps; i >= 0; --i) {
-      rc1.H = (i == 0 || i == plan->steps) ? plan->h_half : plan->h_full;
-      if ((e = launch(plan, KIND_ROW, bytes1, st, [&] { return shape1.row(rc1, rows1, st); })) !=
-          hipSuccess)
-        return api_fail_hip(e, "k2 launch (adjoint)");
-      if (i > 0) {
-        sa.kappa = plan->kappa[(size_t)(i - 1)];
-        sa.state = plan->adj_states + ((size_t)(s - kept_span0) * plan->steps + (size_t)(i - 1)) * slice;
-        if ((e = launch(plan, KIND_ADJ, 1.5 * bytes1, st,
-                        [&] { return ks.adj_stored(sa, batch, st); })) != hipSuccess)
-          return api_fail_hip(e, "k3_adj_stored launch");
-      }
-    }
-    if ((e = launch(plan, KIND_COL, bytes1, st,
-                    [&] { return shape1.cols->col[ssfm::MODE_LAST](ca, batch, st); })) != hipSuccess)
-      return api_fail_hip(e, "k3 launch (adjoint)");
-  }
-  for (int s = kept_span0 - 1; s >= 0; --s) {
-    aa.ckpt = plan->adj_ckpt + (size_t)s * slice;
-    if ((e = launch(plan, KIND_ADJ, row_bytes, st,
-                    [&] { return ks.adj[ssfm::AMODE_FIRST](aa, st); })) != hipSuccess)
-      return api_fail_hip(e, "k3_adj launch");
-    for (int i = plan->steps; i >= 0; --i) {
-      ra.H = (i == 0 || i == plan->steps) ? plan->h_half : plan->h_full;
-      if ((e = launch(plan, KIND_ROW, row_bytes, st, [&] { return row(ra, rows, st); })) !=
-          hipSuccess)
-        return api_fail_hip(e, "k2 launch");
-      if (i > 0) {
-        aa.kappa = plan->kappa[(size_t)(i - 1)];
-        if ((e = launch(plan, KIND_ADJ, row_bytes, st,
-                        [&] { return ks.adj[ssfm::AMODE_NL](aa, st); })) != hipSuccess)
-          return api_fail_hip(e, "k3_adj launch");
-      }
-    }
-    if ((e = launch(plan, KIND_ADJ, row_bytes, st,
-                    [&] { return ks.adj[ssfm::AMODE_LAST](aa, st); })) != hipSuccess)
-      return api_fail_hip(e, "k3_adj launch");
-  }
-  if ((e = hipMemcpyAsync(grad, cot, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
-      hipSuccess)
-    return api_fail_hip(e, "hipMemcpyAsync (gradient)");
+int ssfm_plan_set_forward_streams(ssfm_plan_t plan, int32_t streams) {
+  ssfm::api_clear_error();
+  if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
+  if (streams < 0 || streams > 2)
+    return api_fail(SSFM_EINVAL, "streams must be 0 (automatic), 1 or 2, got %d", streams);
+  plan->forward_streams = streams;
   return SSFM_OK;
 }
 

@@ -54,6 +54,7 @@ def test_tune_info_layout_and_null_arguments():
     assert lib.ssfm_plan_autotune(None, 4, None, ctypes.byref(info)) == ssfm.SSFM_EINVAL
     assert ssfm.ssfm_last_error()
     assert lib.ssfm_plan_set_state_memory(None, 1 << 20) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_plan_set_forward_streams(None, 1) == ssfm.SSFM_EINVAL
 
 
 def test_status_strings_and_version():

@@ -270,3 +270,36 @@ def test_large_nonlinear_phase(ssfm, n, n_pol):
     cnl = 8 / 9 if n_pol == 2 else 1.0
     want = a0 * np.exp(1j * cnl * 1.3e-3 * leff * 2 * np.sum(np.abs(a0) ** 2, axis=0))
     assert rel(got, want) < TOL, rel(got, want)
+
+
+# ---------------------------------------------------------------------------
+# two concurrent sub-batches: a call whose halves each give >= 2048 wide
+# column tiles runs them on two worker streams; the single-stream call gives
+# the same bits (same per-tile arithmetic, realisation b keeps its noise key)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,batch,forced", [(1 << 16, 128, False), (1 << 16, 129, False),
+                                            (1 << 14, 3, True)])
+def test_two_stream_split_is_bitwise(ssfm, n, batch, forced):
+    print(f"case n={n} batch={batch} forced={forced}", flush=True)
+    ln = link(2, n, spans=2, steps=3)
+    a0 = qam(2, n, seed=batch, batch=2)
+    x = np.concatenate([a0] * ((batch + 1) // 2))[:batch]
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).cuda()
+    plan = ssfm.Plan(ln)
+    try:
+        if forced:
+            plan.set_forward_streams(2)
+        split = t.clone()
+        plan.forward(split, seed=4)
+        plan.set_forward_streams(1)
+        one = t.clone()
+        plan.forward(one, seed=4)
+        torch.cuda.synchronize()
+        assert torch.equal(split, one)
+        got = split.cpu().numpy().astype(np.complex128)
+    finally:
+        plan.close()
+    for b in (0, batch - 1):
+        want = oracle.propagate(x[b], ln, seed=4, realization=b)
+        assert rel(got[b], want) < 2e-6, (b, rel(got[b], want))
