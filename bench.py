@@ -458,8 +458,7 @@ def main() -> int:
     # the shapes do not change results)
     tuned = {}
     if not args.no_autotune:
-        # (a call of batch B >= 128 runs as two concurrent sub-batches of B/2)
-        for bsz in sorted({batch, batch // 2, 64, 32, 1} - {0}):
+        for bsz in sorted({batch, 64, 1}):
             if bsz <= batch:
                 tuned[bsz] = plan.autotune(bsz, stream)
                 log(f"autotune batch {bsz}: columns {tuned[bsz]['columns']}, row workgroup "
@@ -473,11 +472,8 @@ def main() -> int:
         plan.forward(field, seed=w.ase_seed, stream=stream)
     torch.cuda.synchronize()
 
-    # the library's rule for splitting a four-step call into two sub-batches
-    sub_batches = 2 if (info.get("path") == 2 and
-                        (batch // 2) * (info["n2"] // info["columns_per_tile"]) >= 2048) else 1
-    # ---- timed region: K calls as the library runs them (at this batch: two
-    # concurrent sub-batches on worker streams, joined into this stream) ------
+    sub_batches = 1  # the library's default: one stream per call
+    # ---- timed region: K calls as the library runs them ---------------------
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
@@ -494,8 +490,7 @@ def main() -> int:
         f"{value:.4e} sample-steps/s")
 
     # ---- kernel rates: K single-stream calls with HIP events around every
-    # launch on the launch stream (concurrent sub-batches would overlap the
-    # launches and blur their durations) -----------------------------------
+    # launch on the launch stream (the events also turn graph replay off) ----
     plan.set_forward_streams(1)
     ssfm.ssfm_profile_begin(plan.handle)
     torch.cuda.synchronize()

@@ -159,17 +159,20 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
                  int64_t batch, uint64_t seed, void* stream);
 
 /* Concurrent sub-batches of a four-step call (n_samples >= 2^14):
- *   0  automatic (the default): ssfm_forward, ssfm_forward_spans and
- *      ssfm_adjoint split the batch into two halves when each half still
- *      gives at least 2048 wide column tiles (batch >= 128 at 2^16 samples);
- *   1  never split;  2  split whenever batch >= 2.
- * The halves run on two worker streams of the device (created on first use,
- * shared with ssfm_batch, default priority), forked from the caller's
- * stream and joined back into it with events, so the call stays ordered on
- * that stream; realisation b keeps its noise key.  Results are the same bit
- * for bit either way (the halves run the same per-tile arithmetic).  A split
- * call does not use graph replay.  Not to be changed while a call on the
- * plan runs.  Errors: SSFM_EINVAL (NULL plan, streams outside 0..2). */
+ *   0 or 1  one stream (the default);
+ *   2       ssfm_forward, ssfm_forward_spans and ssfm_adjoint split a batch
+ *           of two or more realisations into two halves, one on the caller's
+ *           stream and one on a worker stream of the device (created on
+ *           first use, shared with ssfm_batch, default priority) forked from
+ *           the caller's stream and joined back into it with events, so the
+ *           call stays ordered on that stream.
+ * Realisation b keeps its noise key and the halves run the same per-tile
+ * arithmetic, so results are the same bit for bit either way.  Whether the
+ * split is faster depends on the two streams reaching the GPU through
+ * different hardware queues, which the process's stream creation order
+ * decides.  A split call does not use graph replay.  Not to be changed while
+ * a call on the plan runs.  Errors: SSFM_EINVAL (NULL plan, streams outside
+ * 0..2). */
 int ssfm_plan_set_forward_streams(ssfm_plan_t plan, int32_t streams);
 
 /* Device memory, in bytes, that ssfm_adjoint may hold for the kept spans'

@@ -304,7 +304,7 @@ def ssfm_plan_set_state_memory(plan: int, nbytes: int) -> None:
 
 
 def ssfm_plan_set_forward_streams(plan: int, streams: int) -> None:
-    """Concurrent sub-batches of a four-step call: 0 automatic, 1 or 2."""
+    """Concurrent sub-batches of a four-step call: 0 or 1 (one stream), 2."""
     _check(load_library().ssfm_plan_set_forward_streams(plan, int(streams)),
            "ssfm_plan_set_forward_streams")
 
@@ -388,7 +388,7 @@ class Plan:
         return ssfm_plan_autotune(self.handle, batch, stream)
 
     def set_forward_streams(self, streams: int) -> None:
-        """Concurrent sub-batches of a four-step call: 0 automatic, 1 or 2."""
+        """Concurrent sub-batches of a four-step call: 0 or 1 (one stream), 2."""
         ssfm_plan_set_forward_streams(self.handle, streams)
 
     def set_state_memory(self, nbytes: int) -> None:

@@ -118,8 +118,8 @@ struct ssfm_plan_s {
   uint64_t state_budget = 0;
   float2* adj_states = nullptr;
   size_t adj_states_bytes = 0;
-  // concurrent sub-batches of a four-step call: 0 automatic, 1 or 2
-  // (ssfm_plan_set_forward_streams)
+  // concurrent sub-batches of a four-step call: 0 or 1 (one stream, the
+  // default) or 2 (ssfm_plan_set_forward_streams)
   int forward_streams = 0;
 
   ~ssfm_plan_s() {
@@ -521,42 +521,39 @@ int cached_plan(const ssfm_link& key, int device, ssfm_plan_t* out) {
 
 namespace {
 
-// Sub-batches a four-step call runs concurrently: two when each half still
-// gives at least 2048 wide column tiles, else one; the plan's setting
-// (ssfm_plan_set_forward_streams) overrides.  Two sub-batches on two streams
-// fill the tail of each pass and the gap between dependent launches with the
-// other sub-batch's work.
+// Sub-batches a four-step call runs concurrently: one unless the plan asks
+// for two (ssfm_plan_set_forward_streams) and the batch has two realisations.
+// Two sub-batches on two streams can fill the tail of each pass and the gap
+// between dependent launches with the other sub-batch's work, when the two
+// streams reach the GPU through different hardware queues (which the streams'
+// creation order decides, not this library).
 int forward_parts(const ssfm_plan_s* p, int64_t batch) {
   if (p->ks.path != 2 || batch < 2) return 1;
-  if (p->forward_streams == 1 || p->forward_streams == 2) return p->forward_streams;
-  const int64_t tiles = (int64_t)p->ks.n2 / p->ks.wide.columns;
-  return (batch / 2) * tiles >= 2048 ? 2 : 1;
+  return p->forward_streams == 2 ? 2 : 1;
 }
 
-// Run part(h, stream) for h = 0, 1 on two worker streams forked from st and
-// joined back into it (also after an error, so that no work is left
-// unordered).
+// Run part(0, st) on the caller's stream and part(1, w) on a worker stream w
+// forked from st and joined back into it (also after an error, so that no
+// work is left unordered).
 template <typename F>
 int run_split(ssfm_plan_s* p, hipStream_t st, F&& part) {
   hipStream_t ws[kBatchStreams];
   int rc = batch_streams(p->device, ws);
   if (rc != SSFM_OK) return rc;
-  hipEvent_t ev[3] = {};
+  hipEvent_t ev[2] = {};
   hipError_t e = hipSuccess;
-  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(ev[2], st);  // fork
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ws[k], ev[2], 0);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], st);  // fork
+  if (e == hipSuccess) e = hipStreamWaitEvent(ws[0], ev[0], 0);
   if (e != hipSuccess) {
     for (hipEvent_t x : ev)
       if (x) (void)hipEventDestroy(x);
     return api_fail_hip(e, "sub-batch fork");
   }
-  for (int h = 0; h < 2 && rc == SSFM_OK; ++h) rc = part(h, ws[h]);
-  hipError_t ej = hipSuccess;
-  for (int k = 0; k < 2; ++k) {
-    if (ej == hipSuccess) ej = hipEventRecord(ev[k], ws[k]);
-    if (ej == hipSuccess) ej = hipStreamWaitEvent(st, ev[k], 0);
-  }
+  rc = part(1, ws[0]);
+  if (rc == SSFM_OK) rc = part(0, st);
+  hipError_t ej = hipEventRecord(ev[1], ws[0]);  // join
+  if (ej == hipSuccess) ej = hipStreamWaitEvent(st, ev[1], 0);
   for (hipEvent_t x : ev) (void)hipEventDestroy(x);
   if (rc != SSFM_OK) return rc;
   if (ej != hipSuccess) return api_fail_hip(ej, "sub-batch join");
@@ -752,8 +749,8 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch, uint64_t se
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (forward_parts(plan, batch) > 1) {
-    // two sub-batches on worker streams (no graph replay: at such batches
-    // the launches are long against their issue cost)
+    // two sub-batches, on the caller's stream and a worker stream (no graph
+    // replay: the two streams' launches interleave)
     const int64_t b0 = batch / 2;
     float2* f = static_cast<float2*>(field);
     const size_t o = (size_t)b0 * plan->n_pol * plan->n;
@@ -869,8 +866,8 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
     }
     if (kept > 0) plan->adj_states_bytes = (size_t)kept * span_state_bytes;
   }
-  // two concurrent sub-batches (as a forward call of this batch would run)
-  // on carved halves of the workspace, else one
+  // two concurrent sub-batches (when the plan asks for them) on carved
+  // halves of the workspace, else one
   if (forward_parts(plan, batch) == 1)
     return run_adjoint(plan, field_in, grad, batch, seed, 0, st, plan->adj_work, plan->adj_ckpt,
                        plan->adj_states, kept);
@@ -892,7 +889,7 @@ int ssfm_plan_set_forward_streams(ssfm_plan_t plan, int32_t streams) {
   ssfm::api_clear_error();
   if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
   if (streams < 0 || streams > 2)
-    return api_fail(SSFM_EINVAL, "streams must be 0 (automatic), 1 or 2, got %d", streams);
+    return api_fail(SSFM_EINVAL, "streams must be 0 (default), 1 or 2, got %d", streams);
   plan->forward_streams = streams;
   return SSFM_OK;
 }
