@@ -232,6 +232,23 @@ def bench_mixed_batch(args) -> int:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    # parity sample: one call on the inputs, then per length group the entry
+    # with the most spans against the FP64 oracle
+    ssfm.ssfm_batch(links, fields, seeds, 0, stream)
+    torch.cuda.synchronize()
+    rel_errs = {}
+    import oracle
+    for n in sorted({ln.n_samples for ln in links}):
+        k = max((i for i, ln in enumerate(links) if ln.n_samples == n),
+                key=lambda i: links[i].n_spans)
+        want = oracle.propagate(inputs[k], links[k], seed=seeds[k], realization=0)
+        got = fields[k].cpu().numpy().astype(np.complex128)
+        rel_errs[f"entry{k}_n{n}_spans{links[k].n_spans}"] = float(
+            np.linalg.norm(got - want) / np.linalg.norm(want))
+    log(f"workload 4 parity sample: {rel_errs}")
+    for f, a in zip(fields, inputs):
+        f.copy_(torch.from_numpy(a.astype(np.complex64)))
+    torch.cuda.synchronize()
     ms_batch = timed(lambda: ssfm.ssfm_batch(links, fields, seeds, 0, stream), args.steps)
     plans = {}
     for ln in links:
@@ -258,6 +275,7 @@ def bench_mixed_batch(args) -> int:
                    "sample_steps_per_pass": work, "parallelism": "single-gpu"},
         "one_at_a_time": {"ms_per_pass": round(ms_loop, 3), "sample_steps_per_s": loop_rate},
         "batched_speedup": round(ms_loop / ms_batch, 3),
+        "rel_err_vs_oracle": max(rel_errs.values()), "rel_err_sampled": rel_errs,
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -535,16 +553,19 @@ def main() -> int:
     if args.adjoint:
         grad = field.clone()
 
-        def time_adjoint(label):
+        def time_adjoint(label, reps=3):
             plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)  # workspace + warm-up
             torch.cuda.synchronize()
-            a0 = torch.cuda.Event(enable_timing=True)
-            a1 = torch.cuda.Event(enable_timing=True)
-            a0.record(stream)
-            plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
-            a1.record(stream)
-            torch.cuda.synchronize()
-            ms = a0.elapsed_time(a1)
+            times = []
+            for _ in range(reps):
+                a0 = torch.cuda.Event(enable_timing=True)
+                a1 = torch.cuda.Event(enable_timing=True)
+                a0.record(stream)
+                plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
+                a1.record(stream)
+                torch.cuda.synchronize()
+                times.append(a0.elapsed_time(a1))
+            ms = sorted(times)[len(times) // 2]  # median
             # per-kernel breakdown of one more call (events around every launch)
             ssfm.ssfm_profile_begin(plan.handle)
             plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
@@ -553,14 +574,20 @@ def main() -> int:
                 log(f"  adjoint call ({label}) {s_['name']}: {s_['launches']} launches, "
                     f"{s_['total_ms']:.1f} ms, "
                     f"{s_['field_bytes'] / (s_['total_ms'] * 1e-3) / 1e9:.1f} GB/s algorithmic")
-            log(f"forward+adjoint ({label}): {ms:.3f} ms ({ms / ms_per_step:.2f}x forward)")
-            return ms
+            log(f"forward+adjoint ({label}): median {ms:.3f} ms of {reps} "
+                f"({', '.join(f'{t:.1f}' for t in times)}), {ms / ms_per_step:.2f}x forward")
+            return ms, times
 
-        # reverse sweep rebuilding every span's states from its checkpoint
-        ms_rebuild = time_adjoint("span checkpoints")
-        adj = {"fwd_adjoint_ms": round(ms_rebuild, 3),
+        # the headline: span checkpoints, every span's states rebuilt inside
+        # the reverse sweep (no stored states)
+        plan.set_state_memory(0)
+        ms_rebuild, t_rebuild = time_adjoint("span checkpoints, in-span rebuild")
+        adj = {"scheme": "span checkpoints + in-span recomputation (no stored states)",
+               "fwd_adjoint_ms": round(ms_rebuild, 3),
                "ratio_to_forward": round(ms_rebuild / ms_per_step, 3),
-               "rebuild_ms": round(ms_rebuild, 3), "kept_spans": 0}
+               "timed_calls_ms": [round(t, 3) for t in t_rebuild],
+               "workspace_gib": round((link.n_spans + 2) * batch * p * n * 8 / 2 ** 30, 2),
+               "kept_state": None}
         # trailing spans kept: their nonlinear-step inputs stored by the forward
         if args.adjoint_state_gib != 0:
             span_bytes = link.steps_per_span * batch * link.n_pol * link.n_samples * 8
@@ -571,12 +598,17 @@ def main() -> int:
             kept = min(link.n_spans, budget // span_bytes)
             if kept > 0:
                 plan.set_state_memory(kept * span_bytes)
-                ms_kept = time_adjoint(f"{kept} of {link.n_spans} spans kept")
+                ms_kept, t_kept = time_adjoint(f"{kept} of {link.n_spans} spans kept")
                 plan.set_state_memory(0)
-                adj.update({"fwd_adjoint_ms": round(ms_kept, 3),
-                            "ratio_to_forward": round(ms_kept / ms_per_step, 3),
-                            "kept_spans": int(kept),
-                            "state_gib": round(kept * span_bytes / 2 ** 30, 1)})
+                # a different scheme (memory for work), reported beside the
+                # headline, never in its place
+                adj["kept_state"] = {
+                    "scheme": "nonlinear-step inputs of the last spans stored by the forward",
+                    "fwd_adjoint_ms": round(ms_kept, 3),
+                    "ratio_to_forward": round(ms_kept / ms_per_step, 3),
+                    "timed_calls_ms": [round(t, 3) for t in t_kept],
+                    "kept_spans": int(kept),
+                    "state_gib": round(kept * span_bytes / 2 ** 30, 1)}
         del grad
 
     # ---- one field (batch 1): the latency-bound figure ----------------------
@@ -631,15 +663,19 @@ def main() -> int:
                 plan.set_state_memory(kept64 * span64)
                 plan.adjoint(f64, g64, seed=w.ase_seed, stream=stream)  # store + warm-up
                 torch.cuda.synchronize()
-                e0.record(stream)
-                plan.adjoint(f64, g64, seed=w.ase_seed, stream=stream)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                ms64a = e0.elapsed_time(e1)
+                t64 = []
+                for _ in range(3):
+                    e0.record(stream)
+                    plan.adjoint(f64, g64, seed=w.ase_seed, stream=stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    t64.append(e0.elapsed_time(e1))
+                ms64a = sorted(t64)[1]
                 plan.set_state_memory(0)
-                b64.update({"fwd_adjoint_ms": round(ms64a, 3),
-                            "fwd_adjoint_ratio": round(ms64a / ms64, 3),
-                            "kept_spans": int(kept64)})
+                b64.update({"kept_state_fwd_adjoint_ms": round(ms64a, 3),
+                            "kept_state_fwd_adjoint_ratio": round(ms64a / ms64, 3),
+                            "kept_spans": int(kept64),
+                            "state_gib": round(kept64 * span64 / 2 ** 30, 1)})
                 log(f"batch 64 forward+adjoint, {kept64} of {link.n_spans} spans kept: "
                     f"{ms64a:.3f} ms ({ms64a / ms64:.2f}x forward)")
                 del g64

@@ -75,8 +75,12 @@ typedef struct ssfm_link {
 } ssfm_link;
 
 /* Opaque plan: device tables (dispersion operator, twiddles) for one link on
- * one device.  Immutable after creation, so one plan may serve concurrent
- * calls on several streams of its device. */
+ * one device.  The tables are immutable after creation, so forward calls
+ * (ssfm_forward, ssfm_forward_spans) on one plan may run concurrently on
+ * several streams of its device.  ssfm_adjoint calls on one plan share the
+ * plan's adjoint workspace and are serialised by the library (see there).
+ * ssfm_plan_autotune, ssfm_plan_set_forward_streams and the profiling window
+ * change the plan: they must not overlap other calls on it. */
 typedef struct ssfm_plan_s* ssfm_plan_t;
 
 /* Plan description, for callers that report what will run. */
@@ -152,6 +156,11 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
  * Workspace: (n_spans + 2) * batch * n_pol * n_samples * 8 bytes, plus the
  * kept spans' states, allocated on first use (and grown) and owned by the
  * plan; if the device refuses the states' allocation, fewer spans are kept.
+ * Calls on one plan are serialised, since they share that workspace: on the
+ * host by a lock, and on the device by an event, so each call's work starts
+ * after the previous call's work has finished, whatever stream each runs on
+ * (concurrent calls on several streams give the results of consecutive
+ * ones).  Growing the workspace waits for the previous call to finish.
  * Asynchronous like ssfm_forward.  Errors: SSFM_EINVAL (NULL/misaligned
  * pointers, batch < 1), SSFM_EUNSUPPORTED for n_samples < 2^14
  * (LDS-resident path), SSFM_ENOMEM, SSFM_EHIP. */

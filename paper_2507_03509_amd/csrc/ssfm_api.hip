@@ -16,6 +16,7 @@
 
 #include "ssfm.h"
 #include "host_common.hpp"
+#include "launch_log.hpp"
 #include "ssfm_internal.hpp"
 
 using ssfm::cd;
@@ -80,10 +81,7 @@ struct ssfm_plan_s {
   std::vector<void*> allocations;
   // profiling window: event pairs around each launch
   bool profiling = false;
-  std::vector<hipEvent_t> events;  // pool, reused across windows
-  size_t events_used = 0;
-  std::vector<int> prof_kind;
-  std::vector<double> prof_bytes;
+  ssfm::LaunchLog<hipEvent_t> prof;
   // launch-sequence replay: the last forward call's key and, once the same
   // call repeats, its captured graph
   struct GraphKey {
@@ -121,15 +119,24 @@ struct ssfm_plan_s {
   // concurrent sub-batches of a four-step call: 0 or 1 (one stream, the
   // default) or 2 (ssfm_plan_set_forward_streams)
   int forward_streams = 0;
+  // adjoint calls share the workspace above, so they are serialised: on the
+  // host by adj_mu, on the device by adj_done (each call's stream waits for
+  // the last work of the previous call, whatever stream that ran on)
+  std::mutex adj_mu;
+  hipEvent_t adj_done = nullptr;
+  bool adj_pending = false;
+  // device table allocations made so far (fault injection, SSFM_FAIL_ALLOC)
+  int table_allocs = 0;
 
   ~ssfm_plan_s() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : prof.pool()) (void)hipEventDestroy(e);
     for (void* p : allocations) (void)hipFree(p);
     if (adj_ckpt) (void)hipFree(adj_ckpt);
     if (adj_work) (void)hipFree(adj_work);
     if (adj_states) (void)hipFree(adj_states);
+    if (adj_done) (void)hipEventDestroy(adj_done);
   }
 };
 
@@ -192,12 +199,21 @@ std::vector<cd> twiddles(int64_t M, int64_t count, int64_t stride) {
   return t;
 }
 
+// Fault injection for tests: the value of environment variable `name` as a
+// positive integer, else 0.
+int env_count(const char* name) {
+  const char* v = getenv(name);
+  return v ? std::max(0, atoi(v)) : 0;
+}
+
 template <typename T>
 int upload(ssfm_plan_s* p, T** dst, const std::vector<T>& src) {
   const size_t bytes = src.size() * sizeof(T);
   void* d = nullptr;
-  if (getenv("SSFM_FAIL_ALLOC") && strcmp(getenv("SSFM_FAIL_ALLOC"), "1") == 0)
-    return api_fail(SSFM_ENOMEM, "allocation failure injected by SSFM_FAIL_ALLOC=1");
+  // SSFM_FAIL_ALLOC=k: the plan's k-th table allocation fails
+  const int fail_at = env_count("SSFM_FAIL_ALLOC");
+  if (++p->table_allocs == fail_at)
+    return api_fail(SSFM_ENOMEM, "allocation %d failed (injected by SSFM_FAIL_ALLOC)", fail_at);
   hipError_t e = hipMalloc(&d, bytes);
   if (e != hipSuccess) return api_fail(SSFM_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
   p->allocations.push_back(d);
@@ -267,32 +283,26 @@ int build_tables(ssfm_plan_s* p) {
 enum { KIND_LDS = 0, KIND_ROW = 1, KIND_COL = 2, KIND_ADJ = 3, KIND_COUNT = 4 };
 const char* const kKindName[KIND_COUNT] = {"k1_lds", "k2_rows", "k3_cols", "k3_adj"};
 
-hipError_t next_event(ssfm_plan_s* p, hipEvent_t* ev) {
-  if (p->events_used == p->events.size()) {
-    hipEvent_t e;
-    hipError_t err = hipEventCreate(&e);
-    if (err != hipSuccess) return err;
-    p->events.push_back(e);
-  }
-  *ev = p->events[p->events_used++];
-  return hipSuccess;
-}
-
-// Launch through `fn`, bracketed by events when the plan is profiling.
+// Launch through `fn`, bracketed by events when the plan is profiling.  A
+// launch that fails leaves no record (and frees its event pair).
 template <typename F>
 hipError_t launch(ssfm_plan_s* p, int kind, double bytes, hipStream_t st, F&& fn) {
   if (!p->profiling) return fn();
-  hipEvent_t a, b;
-  hipError_t e = next_event(p, &a);
-  if (e == hipSuccess) e = next_event(p, &b);
-  if (e == hipSuccess) e = hipEventRecord(a, st);
-  if (e != hipSuccess) return e;
-  e = fn();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(b, st);
-  p->prof_kind.push_back(kind);
-  p->prof_bytes.push_back(bytes);
-  return e;
+  hipError_t e = hipSuccess;
+  size_t pair = 0;
+  if (!p->prof.reserve([&](hipEvent_t* ev) { return (e = hipEventCreate(ev)) == hipSuccess; },
+                       &pair))
+    return e;
+  ssfm::LaunchLog<hipEvent_t>::Record r{kind, bytes, pair};
+  e = hipEventRecord(p->prof.before(r), st);
+  if (e == hipSuccess) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(p->prof.after(r), st);
+  if (e != hipSuccess) {
+    p->prof.release(pair);
+    return e;
+  }
+  p->prof.record(pair, kind, bytes);
+  return hipSuccess;
 }
 
 int64_t launches_per_call(const ssfm_plan_s* p) {
@@ -300,10 +310,8 @@ int64_t launches_per_call(const ssfm_plan_s* p) {
   return 1 + (int64_t)p->spans * (p->steps + 1) * 2;
 }
 
-// Column tiles: wide once a batch offers at least two workgroups per compute
-// unit, otherwise narrow.  SSFM_COLUMNS (a tile width among the compiled
-// ones) overrides the choice, for tuning.
-// Launch shape of a four-step call: SSFM_COLUMNS override, else the shape
+// Launch shape of a four-step call: SSFM_COLUMNS override (the width of the
+// wide or the narrow column tile, with the matching row workgroup), else the shape
 // ssfm_plan_autotune recorded for this batch, else wide tiles once the batch
 // gives at least 512 column workgroups.
 struct Shape4 {
@@ -316,9 +324,9 @@ Shape4 pick_shape(ssfm_plan_s* p, int64_t batch) {
   const char* env = getenv("SSFM_COLUMNS");
   if (env) {
     const int c = atoi(env);
-    for (const ssfm::FourStepKernels* k : {&p->ks.wide, &p->ks.mid, &p->ks.narrow})
+    for (const ssfm::FourStepKernels* k : {&p->ks.wide, &p->ks.narrow})
       if (k->columns == c) {
-        const bool w = k != &p->ks.narrow;
+        const bool w = k == &p->ks.wide;
         return {k, w ? p->ks.row_wide : p->ks.row_narrow, w, w};
       }
   }
@@ -674,6 +682,75 @@ int run_adjoint(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t bat
 }
 
 
+// ssfm_adjoint with the plan's adjoint lock held and the stream ordered after
+// the previous adjoint call.
+int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t batch,
+                       uint64_t seed, hipStream_t st) {
+  const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
+  const size_t ckpt_bytes = (size_t)plan->spans * slice * sizeof(float2);
+  const size_t work_bytes = 2 * slice * sizeof(float2);
+  if (ckpt_bytes > plan->adj_ckpt_bytes || work_bytes > plan->adj_work_bytes) {
+    // grow the workspace, once the previous call's work is done with it
+    if (plan->adj_pending) {
+      const hipError_t e = hipEventSynchronize(plan->adj_done);
+      if (e != hipSuccess) return api_fail_hip(e, "hipEventSynchronize (adjoint workspace)");
+    }
+    if (plan->adj_ckpt) (void)hipFree(plan->adj_ckpt);
+    if (plan->adj_work) (void)hipFree(plan->adj_work);
+    plan->adj_ckpt = plan->adj_work = nullptr;
+    plan->adj_ckpt_bytes = plan->adj_work_bytes = 0;
+    if (hipMalloc(&plan->adj_ckpt, ckpt_bytes) != hipSuccess ||
+        hipMalloc(&plan->adj_work, work_bytes) != hipSuccess) {
+      if (plan->adj_ckpt) (void)hipFree(plan->adj_ckpt);
+      plan->adj_ckpt = nullptr;
+      return api_fail(SSFM_ENOMEM, "adjoint workspace of %zu bytes", ckpt_bytes + work_bytes);
+    }
+    plan->adj_ckpt_bytes = ckpt_bytes;
+    plan->adj_work_bytes = work_bytes;
+  }
+  // trailing spans whose nonlinear-step inputs the forward pass keeps, as
+  // many as the plan's state budget holds (grown on demand; an allocation
+  // the device refuses lowers the count)
+  const size_t span_state_bytes = (size_t)plan->steps * slice * sizeof(float2);
+  int kept = (int)std::min<uint64_t>((uint64_t)plan->spans, plan->state_budget / span_state_bytes);
+  if ((size_t)kept * span_state_bytes > plan->adj_states_bytes) {
+    if (plan->adj_pending) {
+      const hipError_t e = hipEventSynchronize(plan->adj_done);
+      if (e != hipSuccess) return api_fail_hip(e, "hipEventSynchronize (adjoint states)");
+    }
+    if (plan->adj_states) (void)hipFree(plan->adj_states);
+    plan->adj_states = nullptr;
+    plan->adj_states_bytes = 0;
+    // SSFM_FAIL_STATE_ALLOC=k (tests): a store of more than k spans is refused
+    const int fail_above = env_count("SSFM_FAIL_STATE_ALLOC");
+    while (kept > 0 && ((fail_above > 0 && kept > fail_above) ||
+                        hipMalloc(&plan->adj_states, (size_t)kept * span_state_bytes) != hipSuccess)) {
+      (void)hipGetLastError();
+      plan->adj_states = nullptr;
+      --kept;
+    }
+    if (kept > 0) plan->adj_states_bytes = (size_t)kept * span_state_bytes;
+  }
+  // two concurrent sub-batches (when the plan asks for them) on carved
+  // halves of the workspace, else one
+  if (forward_parts(plan, batch) == 1)
+    return run_adjoint(plan, field_in, grad, batch, seed, 0, st, plan->adj_work, plan->adj_ckpt,
+                       plan->adj_states, kept);
+  const int64_t b0 = batch / 2;
+  const size_t elems = (size_t)plan->n_pol * plan->n;
+  const int64_t sub[2] = {b0, batch - b0};
+  const int64_t off[2] = {0, b0};
+  return run_split(plan, st, [&](int h, hipStream_t ws) {
+    const size_t o = (size_t)off[h] * elems;
+    return run_adjoint(plan, static_cast<const float2*>(field_in) + o, static_cast<float2*>(grad) + o,
+                       sub[h], seed, (uint64_t)off[h], ws, plan->adj_work + 2 * o,
+                       plan->adj_ckpt + (size_t)plan->spans * o,
+                       plan->adj_states ? plan->adj_states + (size_t)kept * plan->steps * o : nullptr,
+                       kept);
+  });
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -832,58 +909,25 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
   DeviceGuard guard(plan->device);
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
-  const size_t ckpt_bytes = (size_t)plan->spans * slice * sizeof(float2);
-  const size_t work_bytes = 2 * slice * sizeof(float2);
-  if (ckpt_bytes > plan->adj_ckpt_bytes || work_bytes > plan->adj_work_bytes) {
-    // grow the workspace (hipFree waits for work still using the old one)
-    if (plan->adj_ckpt) (void)hipFree(plan->adj_ckpt);
-    if (plan->adj_work) (void)hipFree(plan->adj_work);
-    plan->adj_ckpt = plan->adj_work = nullptr;
-    plan->adj_ckpt_bytes = plan->adj_work_bytes = 0;
-    if (hipMalloc(&plan->adj_ckpt, ckpt_bytes) != hipSuccess ||
-        hipMalloc(&plan->adj_work, work_bytes) != hipSuccess) {
-      if (plan->adj_ckpt) (void)hipFree(plan->adj_ckpt);
-      plan->adj_ckpt = nullptr;
-      return api_fail(SSFM_ENOMEM, "adjoint workspace of %zu bytes", ckpt_bytes + work_bytes);
-    }
-    plan->adj_ckpt_bytes = ckpt_bytes;
-    plan->adj_work_bytes = work_bytes;
+  std::lock_guard<std::mutex> lock(plan->adj_mu);
+  hipError_t e;
+  if (!plan->adj_done &&
+      (e = hipEventCreateWithFlags(&plan->adj_done, hipEventDisableTiming)) != hipSuccess) {
+    plan->adj_done = nullptr;
+    return api_fail_hip(e, "hipEventCreate (adjoint order)");
   }
-  // trailing spans whose nonlinear-step inputs the forward pass keeps, as
-  // many as the plan's state budget holds (grown on demand; an allocation
-  // the device refuses lowers the count)
-  const size_t span_state_bytes = (size_t)plan->steps * slice * sizeof(float2);
-  int kept = (int)std::min<uint64_t>((uint64_t)plan->spans, plan->state_budget / span_state_bytes);
-  if ((size_t)kept * span_state_bytes > plan->adj_states_bytes) {
-    if (plan->adj_states) (void)hipFree(plan->adj_states);
-    plan->adj_states = nullptr;
-    plan->adj_states_bytes = 0;
-    while (kept > 0 && hipMalloc(&plan->adj_states, (size_t)kept * span_state_bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      plan->adj_states = nullptr;
-      --kept;
-    }
-    if (kept > 0) plan->adj_states_bytes = (size_t)kept * span_state_bytes;
+  // this call starts after the previous adjoint call's work, on any stream
+  if (plan->adj_pending && (e = hipStreamWaitEvent(st, plan->adj_done, 0)) != hipSuccess)
+    return api_fail_hip(e, "hipStreamWaitEvent (adjoint order)");
+  rc = adjoint_serialised(plan, field_in, grad, batch, seed, st);
+  if ((e = hipEventRecord(plan->adj_done, st)) != hipSuccess) {
+    plan->adj_pending = false;
+    return rc != SSFM_OK ? rc : api_fail_hip(e, "hipEventRecord (adjoint order)");
   }
-  // two concurrent sub-batches (when the plan asks for them) on carved
-  // halves of the workspace, else one
-  if (forward_parts(plan, batch) == 1)
-    return run_adjoint(plan, field_in, grad, batch, seed, 0, st, plan->adj_work, plan->adj_ckpt,
-                       plan->adj_states, kept);
-  const int64_t b0 = batch / 2;
-  const size_t elems = (size_t)plan->n_pol * plan->n;
-  const int64_t sub[2] = {b0, batch - b0};
-  const int64_t off[2] = {0, b0};
-  return run_split(plan, st, [&](int h, hipStream_t ws) {
-    const size_t o = (size_t)off[h] * elems;
-    return run_adjoint(plan, static_cast<const float2*>(field_in) + o, static_cast<float2*>(grad) + o,
-                       sub[h], seed, (uint64_t)off[h], ws, plan->adj_work + 2 * o,
-                       plan->adj_ckpt + (size_t)plan->spans * o,
-                       plan->adj_states ? plan->adj_states + (size_t)kept * plan->steps * o : nullptr,
-                       kept);
-  });
+  plan->adj_pending = true;
+  return rc;
 }
+
 
 int ssfm_plan_set_forward_streams(ssfm_plan_t plan, int32_t streams) {
   ssfm::api_clear_error();
@@ -897,11 +941,16 @@ int ssfm_plan_set_forward_streams(ssfm_plan_t plan, int32_t streams) {
 int ssfm_plan_set_state_memory(ssfm_plan_t plan, uint64_t bytes) {
   ssfm::api_clear_error();
   if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
+  std::lock_guard<std::mutex> lock(plan->adj_mu);
   plan->state_budget = bytes;
   if (plan->adj_states && plan->adj_states_bytes > bytes) {
     DeviceGuard guard(plan->device);
     if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
-    (void)hipFree(plan->adj_states);  // waits for work still using it
+    if (plan->adj_pending) {  // the last adjoint call's work may still read it
+      const hipError_t e = hipEventSynchronize(plan->adj_done);
+      if (e != hipSuccess) return api_fail_hip(e, "hipEventSynchronize (adjoint states)");
+    }
+    (void)hipFree(plan->adj_states);
     plan->adj_states = nullptr;
     plan->adj_states_bytes = 0;
   }
@@ -1148,9 +1197,7 @@ int ssfm_plan_autotune(ssfm_plan_t plan, int64_t batch, void* stream, ssfm_tune_
 int ssfm_profile_begin(ssfm_plan_t plan) {
   if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
   plan->profiling = true;
-  plan->events_used = 0;
-  plan->prof_kind.clear();
-  plan->prof_bytes.clear();
+  plan->prof.clear();
   return SSFM_OK;
 }
 
@@ -1160,19 +1207,16 @@ int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int
   DeviceGuard guard(plan->device);
   double ms[KIND_COUNT] = {0, 0, 0, 0}, bytes[KIND_COUNT] = {0, 0, 0, 0};
   int64_t n[KIND_COUNT] = {0, 0, 0, 0};
-  const size_t launches = plan->prof_kind.size();
-  if (launches) {
-    hipError_t e = hipEventSynchronize(plan->events[2 * launches - 1]);
+  // launches may have run on several streams: wait for each closing event
+  for (const auto& r : plan->prof.records()) {
+    hipError_t e = hipEventSynchronize(plan->prof.after(r));
     if (e != hipSuccess) return api_fail_hip(e, "hipEventSynchronize");
-  }
-  for (size_t i = 0; i < launches; ++i) {
     float t = 0.0f;
-    hipError_t e = hipEventElapsedTime(&t, plan->events[2 * i], plan->events[2 * i + 1]);
+    e = hipEventElapsedTime(&t, plan->prof.before(r), plan->prof.after(r));
     if (e != hipSuccess) return api_fail_hip(e, "hipEventElapsedTime");
-    const int k = plan->prof_kind[i];
-    ms[k] += t;
-    bytes[k] += plan->prof_bytes[i];
-    n[k] += 1;
+    ms[r.kind] += t;
+    bytes[r.kind] += r.bytes;
+    n[r.kind] += 1;
   }
   int w = 0;
   for (int k = 0; k < KIND_COUNT && w < capacity; ++k) {
@@ -1185,9 +1229,7 @@ int ssfm_profile_end(ssfm_plan_t plan, ssfm_kernel_stats* out, int capacity, int
     ++w;
   }
   *count = w;
-  plan->events_used = 0;
-  plan->prof_kind.clear();
-  plan->prof_bytes.clear();
+  plan->prof.clear();
   return SSFM_OK;
 }
 

@@ -108,8 +108,8 @@ struct KernelSet {
   LdsLaunch lds = nullptr;
   RowLaunch row_wide = nullptr, row_narrow = nullptr;
   int rows_wide = 0, rows_narrow = 0;  // rows per workgroup
-  // column tiles: narrow (2 columns), mid, wide
-  FourStepKernels narrow, mid, wide;
+  // column tiles: narrow (2 columns) and wide (8, or 4 at N1 = 512)
+  FourStepKernels narrow, wide;
   AdjLaunch adj[3] = {nullptr, nullptr, nullptr};
   int adj_columns = 0;
   AdjStoredLaunch adj_stored = nullptr;

@@ -383,15 +383,9 @@ static void fill_k3(FourStepKernels& k) {
 template <int N1, int P>
 static void fill_cols(KernelSet& ks) {
   // FFT exchanges in FP64 LDS, 64 KB per workgroup for the wide tiles: 8 (4 at
-  // N1 = 512) adjacent columns, 64/32-byte row segments; mid tiles: half of
-  // that; narrow tiles: 2 columns, for batches too small to fill the chip
-  if constexpr (N1 == 512) {
-    fill_k3<N1, 4, P, cd>(ks.wide);
-    fill_k3<N1, 8, P, float2>(ks.mid);
-  } else {
-    fill_k3<N1, 8, P, cd>(ks.wide);
-    fill_k3<N1, 16, P, float2>(ks.mid);
-  }
+  // N1 = 512) adjacent columns, 64/32-byte row segments; narrow tiles: 2
+  // columns, for batches too small to fill the chip
+  fill_k3<N1, N1 == 512 ? 4 : 8, P, cd>(ks.wide);
   fill_k3<N1, 2, P, cd>(ks.narrow);
 }
 
@@ -440,7 +434,7 @@ bool select_kernels(int64_t n, int n_pol, KernelSet& ks) {
       break;
     default: return false;
   }
-  for (const FourStepKernels* k : {&ks.wide, &ks.mid, &ks.narrow})
+  for (const FourStepKernels* k : {&ks.wide, &ks.narrow})
     if (k->prepare_status != hipSuccess) ks.prepare = k->prepare_status;
   select_adjoint_kernels(ks.n1, n_pol, ks);
   return true;

@@ -8,6 +8,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle
+from fieldcheck import check, rel
 from workloads import Link, batch_config, dual_pol_field
 
 pytestmark = pytest.mark.gpu
@@ -22,8 +23,6 @@ def ssfm():
     return m
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
 def entries(n_entries, steps, seed=0):
@@ -55,8 +54,8 @@ def test_batch_matches_oracle_and_single_calls(ssfm):
         plan.close()
         got = f.cpu().numpy().astype(np.complex128)
         want = oracle.propagate(a, ln, seed=s, realization=0)
-        assert rel(got, want) < 2e-6, (ln.n_samples, ln.n_spans, rel(got, want))
-        assert rel(got, g.cpu().numpy().astype(np.complex128)) < 1e-6
+        check(got, want, 2e-6)
+        check(got, g.cpu().numpy().astype(np.complex128), 1e-6)
 
 
 def test_batch_workload4_shapes_run(ssfm):
@@ -76,7 +75,7 @@ def test_batch_workload4_shapes_run(ssfm):
     torch.cuda.synchronize()
     for k in (0, 5, 17):
         want = oracle.propagate(inputs[k], links[k], seed=seeds[k], realization=0)
-        assert rel(fields[k].cpu().numpy().astype(np.complex128), want) < 2e-6
+        check(fields[k].cpu().numpy().astype(np.complex128), want, 2e-6)
 
 
 def test_batch_rejects_invalid_entries(ssfm):
@@ -118,3 +117,31 @@ def test_batch_groups_concurrent_bitwise(ssfm):
         torch.cuda.synchronize()
         plan.close()
         assert np.array_equal(runs[0][k], g.cpu().numpy()), (k, ln.n_samples)
+
+
+def test_batch_workload4_full_size(ssfm):
+    # workload 4 as stated: 256 realisations, 50 steps per span, 1..10 spans,
+    # lengths 2^12..2^16.  Per length group, the entry with the fewest spans
+    # (it runs only in the group's first segment, the widest: seeded wide
+    # tiles on the four-step lengths) and the one with the most (every
+    # segment, down to the narrow tiles of the last ones) against the oracle
+    items = batch_config(256)
+    rng = np.random.default_rng(20250703 + 44)
+    links = [it.link() for it in items]
+    assert all(ln.steps_per_span == 50 for ln in links)
+    inputs = [dual_pol_field(rng, 2, ln.n_samples, 2, 64e9, 0.1, it.launch_dbm)
+              for it, ln in zip(items, links)]
+    seeds = [it.seed for it in items]
+    fields = [torch.from_numpy(a.astype(np.complex64)).cuda() for a in inputs]
+    ssfm.ssfm_batch(links, fields, seeds, 0)
+    torch.cuda.synchronize()
+    picked = []
+    for n in sorted({ln.n_samples for ln in links}):
+        idx = [i for i, ln in enumerate(links) if ln.n_samples == n]
+        picked += sorted({min(idx, key=lambda i: links[i].n_spans),
+                          max(idx, key=lambda i: links[i].n_spans)})
+    assert len(picked) >= 9
+    for k in picked:
+        print(f"entry {k}: n={links[k].n_samples} spans={links[k].n_spans}", flush=True)
+        want = oracle.propagate(inputs[k], links[k], seed=seeds[k], realization=0)
+        check(fields[k].cpu().numpy().astype(np.complex128), want, 2e-6, what=f"entry {k}")
