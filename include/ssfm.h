@@ -167,6 +167,29 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
 int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
                  int64_t batch, uint64_t seed, void* stream);
 
+/* ssfm_adjoint for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and result as ssfm_adjoint, computed by the same kernels in
+ * the same order (span checkpoints, every span rebuilt: no kept states, and
+ * one stream whatever ssfm_plan_set_forward_streams says), but the work
+ * fields and checkpoints live in a device scratch array of the library
+ * (128 MiB per device, held by every device that loads the library until the
+ * process ends; its address is resolved per device by ssfm_plan).  The call
+ * makes no hipMalloc/hipFree and creates no stream or event.
+ *   Limit: (n_spans + 2) * batch * n_pol * n_samples * 8 bytes <= 128 MiB
+ *   (e.g. batch <= 10 for 2^16 samples x 2 pol x 10 spans); larger calls
+ *   return SSFM_EINVAL before any device work.
+ * Every call on a device shares that device's one scratch array, whatever
+ * the plan: calls that overlap on one device (two streams, two threads, two
+ * plans) race and give wrong results; the caller must order them.  Nothing
+ * in the scratch needs to start at zero (each call writes what it reads).
+ * Errors: those of ssfm_adjoint, SSFM_EINVAL also for the size limit and
+ * while a profiling window is open on the plan, SSFM_EUNSUPPORTED for
+ * n_samples < 2^14, SSFM_EHIP if the scratch address could not be
+ * resolved. */
+int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad,
+                         int64_t batch, uint64_t seed, void* stream);
+
 /* Concurrent sub-batches of a four-step call (n_samples >= 2^14):
  *   0 or 1  one stream (the default);
  *   2       ssfm_forward, ssfm_forward_spans and ssfm_adjoint split a batch

@@ -20,8 +20,8 @@ from typing import Optional
 __all__ = [
     "SsfmLink", "SsfmPlanInfo", "SsfmError", "library_path", "load_library",
     "make_link", "ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info",
-    "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch",
-    "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
+    "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_adjoint_noalloc",
+    "ssfm_batch", "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
     "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats", "propagate",
     "SsfmTuneInfo", "ssfm_plan_autotune", "ssfm_stream_copy", "ssfm_dft16_rounds",
     "ssfm_plan_set_state_memory", "ssfm_plan_set_forward_streams",
@@ -135,6 +135,7 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_forward.argtypes = [P, VP, I64, U64, VP]
     lib.ssfm_forward_spans.argtypes = [P, VP, I64, U64, U64, I32, I32, VP]
     lib.ssfm_adjoint.argtypes = [P, VP, VP, I64, U64, VP]
+    lib.ssfm_adjoint_noalloc.argtypes = [P, VP, VP, I64, U64, VP]
     lib.ssfm_plan_set_state_memory.argtypes = [P, U64]
     lib.ssfm_plan_set_forward_streams.argtypes = [P, I32]
     lib.ssfm_batch.argtypes = [ctypes.POINTER(SsfmLink), ctypes.POINTER(ctypes.c_void_p), I64,
@@ -154,7 +155,7 @@ def load_library() -> ctypes.CDLL:
                  "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version",
                  "ssfm_profile_begin", "ssfm_profile_end", "ssfm_plan_autotune",
                  "ssfm_stream_copy", "ssfm_dft16_rounds", "ssfm_plan_set_state_memory",
-                 "ssfm_plan_set_forward_streams"):
+                 "ssfm_plan_set_forward_streams", "ssfm_adjoint_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -293,6 +294,19 @@ def ssfm_adjoint(plan: int, field_in, grad, seed: int = 0, stream=None) -> None:
         raise ValueError("grad must have the shape of field_in")
     _check(load_library().ssfm_adjoint(plan, ptr, gptr, b, int(seed) & (2 ** 64 - 1),
                                        _stream_ptr(field_in, stream)), "ssfm_adjoint")
+
+
+def ssfm_adjoint_noalloc(plan: int, field_in, grad, seed: int = 0, stream=None) -> None:
+    """ssfm_adjoint with the library's fixed device scratch instead of
+    allocated workspace (no device allocation; calls on one device must not
+    overlap)."""
+    b, ptr = _field_args(field_in)
+    bg, gptr = _field_args(grad)
+    if bg != b or tuple(grad.shape) != tuple(field_in.shape):
+        raise ValueError("grad must have the shape of field_in")
+    _check(load_library().ssfm_adjoint_noalloc(plan, ptr, gptr, b, int(seed) & (2 ** 64 - 1),
+                                               _stream_ptr(field_in, stream)),
+           "ssfm_adjoint_noalloc")
 
 
 def ssfm_plan_set_state_memory(plan: int, nbytes: int) -> None:

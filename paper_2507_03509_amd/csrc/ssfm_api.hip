@@ -59,6 +59,51 @@ constexpr double kPi = 3.14159265358979323846;
 bool finite(double v) { return isfinite(v) != 0; }
 }  // namespace
 
+// Device scratch of ssfm_adjoint_noalloc: the adjoint's work fields and span
+// checkpoints for callers that cannot allocate.  One array per device (each
+// device that loads the library holds it until the process ends).  In host
+// code its name is only a stand-in: kernels and copies take the device
+// address resolved per device by resolve_scratch.
+constexpr size_t kNoallocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct ScratchAddrs {
+  std::mutex mu;
+  void* ptr[kMaxDevices] = {};
+  hipError_t status[kMaxDevices] = {};
+  bool tried[kMaxDevices] = {};
+};
+ScratchAddrs& scratch_addrs() {
+  static ScratchAddrs* a = new ScratchAddrs();  // never destroyed
+  return *a;
+}
+
+// Once per device, with that device current: the device address of
+// `scratch` (called from ssfm_plan).
+void resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  ScratchAddrs& a = scratch_addrs();
+  std::lock_guard<std::mutex> lock(a.mu);
+  if (a.tried[device]) return;
+  a.tried[device] = true;
+  void* ptr = nullptr;
+  a.status[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  a.ptr[device] = a.status[device] == hipSuccess ? ptr : nullptr;
+}
+
+// The resolved address for `device`, or nullptr with the reason in *why.
+void* scratch_ptr(int device, hipError_t* why) {
+  *why = hipErrorInvalidDevice;
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  ScratchAddrs& a = scratch_addrs();
+  std::lock_guard<std::mutex> lock(a.mu);
+  *why = a.tried[device] ? a.status[device] : hipErrorNotInitialized;
+  return a.ptr[device];
+}
+}  // namespace
+
 struct ssfm_plan_s {
   ssfm_link link{};
   int device = 0;
@@ -768,6 +813,9 @@ int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out) {
     return api_fail(SSFM_EINVAL, "hip_device %d out of range (%d devices)", hip_device, count);
   DeviceGuard guard(hip_device);
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
+  // set-up of ssfm_adjoint_noalloc's device scratch (once per device); a
+  // failure is reported by that call, not here
+  resolve_scratch(hip_device);
 
   ssfm_plan_s* p = new (std::nothrow) ssfm_plan_s();
   if (!p) return api_fail(SSFM_ENOMEM, "host allocation of the plan failed");
@@ -926,6 +974,35 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
   }
   plan->adj_pending = true;
   return rc;
+}
+
+int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad, int64_t batch,
+                         uint64_t seed, void* stream) {
+  ssfm::api_clear_error();
+  int rc = check_call(plan, field_in, batch);
+  if (rc != SSFM_OK) return rc;
+  if (!grad) return api_fail(SSFM_EINVAL, "grad is NULL");
+  if (((uintptr_t)grad & 7u) != 0) return api_fail(SSFM_EINVAL, "grad must be 8-byte aligned");
+  if (plan->ks.path != 2)
+    return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint_noalloc needs n_samples >= 2^14 (four-step path)");
+  if (plan->profiling)
+    return api_fail(SSFM_EINVAL, "ssfm_adjoint_noalloc: a profiling window is open on the plan "
+                                 "(its per-launch events would be created here)");
+  // work [2][batch] fields, then checkpoints [spans][batch]
+  const uint64_t slice = (uint64_t)batch * (uint64_t)plan->n_pol * (uint64_t)plan->n;
+  const uint64_t need = ((uint64_t)plan->spans + 2) * slice * sizeof(float2);
+  if (need > kNoallocScratchBytes)
+    return api_fail(SSFM_EINVAL,
+                    "ssfm_adjoint_noalloc: (n_spans + 2) * batch * n_pol * n_samples * 8 = %llu "
+                    "bytes exceeds the %llu-byte device scratch; use ssfm_adjoint or a smaller batch",
+                    (unsigned long long)need, (unsigned long long)kNoallocScratchBytes);
+  hipError_t why;
+  float2* base = static_cast<float2*>(scratch_ptr(plan->device, &why));
+  if (!base) return api_fail_hip(why, "ssfm_adjoint_noalloc: device scratch address");
+  DeviceGuard guard(plan->device);
+  if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
+  return run_adjoint(plan, field_in, grad, batch, seed, 0, static_cast<hipStream_t>(stream), base,
+                     base + 2 * slice, nullptr, 0);
 }
 
 
