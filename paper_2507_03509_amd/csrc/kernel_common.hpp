@@ -80,10 +80,24 @@ __device__ __forceinline__ cd phasor_series(double phi) {
   return {fma(pc, x2, 1.0), fma(ps * x2, phi, phi)};
 }
 
+// exp(i phi) for |phi| <= 1/32, the common case by far (one split step's
+// nonlinear phase is ~1e-3..1e-2 rad here): sin to phi^7 and cos to phi^6,
+// whose truncation (phi^9/9! and phi^8/8!, at most 2.2e-17) is below FP64
+// rounding, in 7 FP64 operations instead of 13.
+constexpr double kShortPhase = 1.0 / 32.0;
+__device__ __forceinline__ cd phasor_short(double phi) {
+  const double x2 = phi * phi;
+  double ps = fma(x2, -1.0 / 5040.0, 1.0 / 120.0);
+  ps = fma(ps, x2, -1.0 / 6.0);
+  double pc = fma(x2, -1.0 / 720.0, 1.0 / 24.0);
+  pc = fma(pc, x2, -0.5);
+  return {fma(pc, x2, 1.0), fma(ps * x2, phi, phi)};
+}
+
 // Any angle: the series at phi / 2^k (halved until |phi / 2^k| <= 1/4),
 // squared k times, then one Newton step on the modulus (k squarings double
-// the relative rounding error k times).  For |phi| <= 1/4 it returns the
-// series' bits unchanged.  Reads no memory.
+// the relative rounding error k times).  Angles within 1/32 get the short
+// series, those within 1/4 the long one.  Reads no memory.
 __device__ __forceinline__ cd unit_phasor_any(double phi) {
   int k = 0;
 #pragma unroll 1
@@ -91,8 +105,8 @@ __device__ __forceinline__ cd unit_phasor_any(double phi) {
     phi *= 0.5;
     ++k;
   }
+  if (k == 0) return fabs(phi) <= kShortPhase ? phasor_short(phi) : phasor_series(phi);
   cd z = phasor_series(phi);
-  if (k == 0) return z;
 #pragma unroll 1
   for (int i = 0; i < k; ++i) z = {(z.re - z.im) * (z.re + z.im), 2.0 * z.re * z.im};
   const double m = fma(z.re, z.re, z.im * z.im);
@@ -100,24 +114,25 @@ __device__ __forceinline__ cd unit_phasor_any(double phi) {
   return {z.re * f, z.im * f};
 }
 
-// rot[r] = exp(i phi[r]), r < 16, out of line: only waves holding a large
-// angle call it, and its registers do not count against the callers'.
+// rot[r] = exp(i phi[r]), r < 16, out of line: only waves holding an angle
+// above 1/32 call it, and its registers do not count against the callers'.
 __device__ __noinline__ void unit_phasors_any16(const double* phi, cd* rot) {
 #pragma unroll 1
   for (int r = 0; r < 16; ++r) rot[r] = unit_phasor_any(phi[r]);
 }
 
 // f(r, exp(i phi[r])) for the 16 angles of a lane.  The branch is uniform
-// over the wave: the series unless some angle of the wave exceeds 1/4, and
-// both branches give the same bits for the small angles, so a result never
-// depends on its neighbours.  (A per-element branch makes the compiler keep
-// registers for both paths across 16 divergent regions.)
+// over the wave: the short series when every angle of the wave is within
+// 1/32, else the general routine, which gives the short series' bits to the
+// angles within 1/32 -- so a result never depends on its neighbours.  (A
+// per-element branch makes the compiler keep registers for both paths across
+// 16 divergent regions.)
 template <typename F>
 __device__ __forceinline__ void for_each_phasor16(const double (&phi)[16], F&& f) {
-  bool big = false;
+  bool wide = false;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) big |= !(fabs(phi[r]) <= 0.25);
-  if (__any(big)) {
+  for (int r = 0; r < 16; ++r) wide |= !(fabs(phi[r]) <= kShortPhase);
+  if (__any(wide)) {
     double ph[16];
     cd rot[16];
 #pragma unroll
@@ -127,8 +142,23 @@ __device__ __forceinline__ void for_each_phasor16(const double (&phi)[16], F&& f
     for (int r = 0; r < 16; ++r) f(r, rot[r]);
   } else {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) f(r, phasor_series(phi[r]));
+    for (int r = 0; r < 16; ++r) f(r, phasor_short(phi[r]));
   }
+}
+
+// Sum of x over the lane pair (l, l ^ 32) of a wave, the same bits on both
+// lanes: v_permlane32_swap exchanges the upper half of one operand with the
+// lower half of the other, so with x in both operands every lane receives
+// the lower lane's x in the first result and the upper lane's in the second,
+// and adds them in that order.
+__device__ __forceinline__ double pair32_sum(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+  const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double lower = __builtin_bit_cast(double, ((uint64_t)rh[0] << 32) | rl[0]);
+  const double upper = __builtin_bit_cast(double, ((uint64_t)rh[1] << 32) | rl[1]);
+  return lower + upper;
 }
 
 // twiddle W_N^m from the two-level table (m < N): twA[a] = W_N^{a N2},

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const int lr = threadIdx.x / T;
   const int j = threadIdx.x % T;
   const int64_t row = (int64_t)blockIdx.x * RPW + lr;
-  const int k1 = (int)(row % n1);
+  const int k1 = (int)(row & (n1 - 1));  // n1 is a power of two
   float2* rp = field + row * N2;
   L* mylds = lds2 + lr * (N2 + N2 / 16);  // padded row: stride = 16 mod 32 slots
   cd reg[16];
@@ -95,10 +95,25 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
   extern __shared__ __align__(16) unsigned char lds3_raw[];
   L* lds3 = reinterpret_cast<L*>(lds3_raw);
   const int tid = threadIdx.x;
-  const int p = tid / (C * T);
-  const int rem = tid % (C * T);
-  const int c = rem % C;
-  const int j = rem / C;
+  // Lane -> (polarisation p, column c, row j).  Two polarisations with at
+  // least 32 lanes each: the two halves of every wave hold the same (c, j)
+  // for p = 0 and p = 1, so the nonlinear step sums the powers across the
+  // lane pair in registers; otherwise the polarisations are consecutive
+  // blocks of C T lanes.
+  constexpr bool PAIR = P == 2 && C * T >= 32;
+  int p, c, j;
+  if constexpr (PAIR) {
+    const int l = tid & 63;
+    const int q = (tid >> 6) * 32 + (l & 31);
+    p = l >> 5;
+    c = q % C;
+    j = q / C;
+  } else {
+    p = tid / (C * T);
+    const int rem = tid % (C * T);
+    c = rem % C;
+    j = rem / C;
+  }
   const int tiles = a.n2 / C;
   // Adjacent column tiles share 128-byte lines.  Workgroups are dispatched
   // round-robin over the 8 XCDs (each with its own L2), so XCD x runs blocks
@@ -131,7 +146,15 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
       for (int r = 0; r < 16; ++r) col_store(sb, r, reg[r]);
     }
     if constexpr (MODE == MODE_NL || MODE == MODE_NL_STORE) {
-      if constexpr (P == 2) {
+      if constexpr (PAIR) {
+        // |a_x|^2 + |a_y|^2 from the lane pair, added x + y on both lanes,
+        // so both rotate by the same phase
+        double phi[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          phi[r] = a.kappa * pair32_sum(fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im));
+        for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
+      } else if constexpr (P == 2) {
         // exchange |a_p|^2 with the lane of the other polarisation (the sum
         // is formed x + y on both lanes, so both rotate by the same phase)
         double* pbuf = reinterpret_cast<double*>(lds3_raw);
