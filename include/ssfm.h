@@ -50,6 +50,18 @@ extern "C" {
 #define SSFM_EHIP (-3)         /* a HIP runtime call or kernel launch failed  */
 #define SSFM_EUNSUPPORTED (-4) /* valid request this build does not implement */
 
+/* ssfm_link.flags: FP32 arithmetic (a precision study variant, forward
+ * only).  The default path computes every step in FP64 registers and rounds
+ * only the stored field to complex64.  With this flag the FFT butterflies,
+ * the twiddle multiplications (with the FP64 twiddle tables rounded to FP32)
+ * and the nonlinear phase rotation (FP32 sine and cosine) run in FP32, while
+ * the dispersion multiply -- the per-step linear operator -- and the span-end
+ * gain and noise stay FP64.  Its error against the FP64 reference grows with
+ * the step count (a fixed rounding of the transform's coefficients repeats at
+ * every step); ssfm_adjoint and ssfm_adjoint_noalloc refuse such plans with
+ * SSFM_EUNSUPPORTED. */
+#define SSFM_FLAG_FP32_ARITHMETIC 1u
+
 /* One amplified fibre link, in the units such links are quoted in.
  * Every span is identical.  The library converts to SI internally:
  * alpha[1/m] = alpha_db_per_km * ln(10)/10 / 1e3 (power attenuation),
@@ -70,7 +82,7 @@ typedef struct ssfm_link {
   double edfa_gain_db;       /* power gain per span end; 0 dB = unity gain    */
   double edfa_nf_db;         /* noise figure, used when ase = 1               */
   double carrier_hz;         /* optical carrier; NaN selects 193.4145 THz     */
-  uint32_t flags;            /* reserved, must be 0                           */
+  uint32_t flags;            /* 0, or SSFM_FLAG_FP32_ARITHMETIC               */
   uint32_t reserved;         /* must be 0                                     */
 } ssfm_link;
 
@@ -120,6 +132,22 @@ int ssfm_plan_get_info(ssfm_plan_t plan, ssfm_plan_info* info);
  * batch < 1), SSFM_EHIP (launch failure). */
 int ssfm_forward(ssfm_plan_t plan, void* field, int64_t batch, uint64_t seed,
                  void* stream);
+
+/* The plan's discrete Fourier transform alone, for checking the transform
+ * stages of the propagation against the DFT's definition: every polarisation
+ * of every realisation of `field` (layout as ssfm_forward) is replaced, in
+ * place, by its unnormalised length-n_samples DFT
+ *   X[k] = sum_t x[t] exp(-+2 pi i t k / n_samples)   (inverse = 0 / 1),
+ * computed by the same FFT stages, in the same arithmetic, as the
+ * propagation: the LDS-resident transform for n_samples <= 2^13; on the
+ * four-step path the column FFT pass and the twiddle + row FFT pass
+ * (inverse: the row IFFT + conjugate twiddle pass, then the column IFFT).
+ * Frequency order: natural on the LDS-resident path; on the four-step path
+ * the passes' own order, bin k = k1 + n1 k2 (k1 < n1, k2 < n2) at position
+ * k1 n2 + k2 (n1, n2 from ssfm_plan_get_info); the inverse takes its input
+ * in that order.  Asynchronous.  Errors: those of ssfm_forward, SSFM_EINVAL
+ * for inverse not 0 or 1. */
+int ssfm_dft(ssfm_plan_t plan, void* field, int64_t batch, int32_t inverse, void* stream);
 
 /* As ssfm_forward, restricted to spans [span_begin, span_end) and with the
  * noise realisation index of batch entry b equal to realization0 + b.  A run

@@ -22,6 +22,6 @@ from .ldbp_ref import (fir, nl_rotate, ldbp_forward, matched_filter_samples,
 __all__ += ["fir", "nl_rotate", "ldbp_forward", "matched_filter_samples",
             "mse_loss", "mse_grad", "ldbp_backward", "init_params"]
 
-from .dft_ref import dft_matrix, dft_direct, dft16_rounds
+from .dft_ref import dft_matrix, dft_direct, dft16_rounds, dft_bins
 
-__all__ += ["dft_matrix", "dft_direct", "dft16_rounds"]
+__all__ += ["dft_matrix", "dft_direct", "dft16_rounds", "dft_bins"]

@@ -20,12 +20,13 @@ from typing import Optional
 __all__ = [
     "SsfmLink", "SsfmPlanInfo", "SsfmError", "library_path", "load_library",
     "make_link", "ssfm_plan", "ssfm_plan_destroy", "ssfm_plan_get_info",
-    "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_adjoint_noalloc",
+    "ssfm_forward", "ssfm_forward_spans", "ssfm_adjoint", "ssfm_adjoint_noalloc", "ssfm_dft",
     "ssfm_batch", "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
     "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats", "propagate",
     "SsfmTuneInfo", "ssfm_plan_autotune", "ssfm_stream_copy", "ssfm_dft16_rounds",
     "ssfm_plan_set_state_memory", "ssfm_plan_set_forward_streams",
     "SSFM_OK", "SSFM_EINVAL", "SSFM_ENOMEM", "SSFM_EHIP", "SSFM_EUNSUPPORTED",
+    "SSFM_FLAG_FP32_ARITHMETIC",
 ]
 
 SSFM_OK = 0
@@ -33,6 +34,7 @@ SSFM_EINVAL = -1
 SSFM_ENOMEM = -2
 SSFM_EHIP = -3
 SSFM_EUNSUPPORTED = -4
+SSFM_FLAG_FP32_ARITHMETIC = 1  # ssfm_link.flags: the FP32-arithmetic variant
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -136,6 +138,7 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_forward_spans.argtypes = [P, VP, I64, U64, U64, I32, I32, VP]
     lib.ssfm_adjoint.argtypes = [P, VP, VP, I64, U64, VP]
     lib.ssfm_adjoint_noalloc.argtypes = [P, VP, VP, I64, U64, VP]
+    lib.ssfm_dft.argtypes = [P, VP, I64, I32, VP]
     lib.ssfm_plan_set_state_memory.argtypes = [P, U64]
     lib.ssfm_plan_set_forward_streams.argtypes = [P, I32]
     lib.ssfm_batch.argtypes = [ctypes.POINTER(SsfmLink), ctypes.POINTER(ctypes.c_void_p), I64,
@@ -155,7 +158,7 @@ def load_library() -> ctypes.CDLL:
                  "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version",
                  "ssfm_profile_begin", "ssfm_profile_end", "ssfm_plan_autotune",
                  "ssfm_stream_copy", "ssfm_dft16_rounds", "ssfm_plan_set_state_memory",
-                 "ssfm_plan_set_forward_streams", "ssfm_adjoint_noalloc"):
+                 "ssfm_plan_set_forward_streams", "ssfm_adjoint_noalloc", "ssfm_dft"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -196,8 +199,9 @@ def _nan_if_none(v) -> float:
     return float("nan") if v is None else float(v)
 
 
-def make_link(link) -> SsfmLink:
-    """``SsfmLink`` from any object with the fields of ``workloads.Link``."""
+def make_link(link, flags: int = 0) -> SsfmLink:
+    """``SsfmLink`` from any object with the fields of ``workloads.Link``;
+    ``flags``: 0 or SSFM_FLAG_FP32_ARITHMETIC."""
     return SsfmLink(
         n_pol=int(link.n_pol), n_spans=int(link.n_spans),
         steps_per_span=int(link.steps_per_span), ase=1 if link.ase else 0,
@@ -209,17 +213,17 @@ def make_link(link) -> SsfmLink:
         edfa_gain_db=float(getattr(link, "edfa_gain_db", 0.0)),
         edfa_nf_db=float(getattr(link, "edfa_nf_db", 0.0)),
         carrier_hz=_nan_if_none(getattr(link, "carrier_hz", None)),
-        flags=0, reserved=0)
+        flags=int(flags), reserved=0)
 
 
 # ---------------------------------------------------------------------------
 # C-ABI mirrors
 # ---------------------------------------------------------------------------
 
-def ssfm_plan(link, hip_device: int = 0) -> int:
+def ssfm_plan(link, hip_device: int = 0, flags: int = 0) -> int:
     """Build a plan; returns the opaque handle (an int)."""
     lib = load_library()
-    s = link if isinstance(link, SsfmLink) else make_link(link)
+    s = link if isinstance(link, SsfmLink) else make_link(link, flags)
     out = ctypes.c_void_p()
     _check(lib.ssfm_plan(ctypes.byref(s), int(hip_device), ctypes.byref(out)), "ssfm_plan")
     return out.value
@@ -283,6 +287,14 @@ def ssfm_forward_spans(plan: int, field, seed: int, realization0: int, span_begi
                                              int(realization0), int(span_begin),
                                              int(span_end), _stream_ptr(field, stream)),
            "ssfm_forward_spans")
+
+
+def ssfm_dft(plan: int, field, inverse: bool = False, stream=None) -> None:
+    """The plan's unnormalised DFT of every polarisation, in place (see
+    ssfm_dft in ssfm.h for the frequency order of the four-step path)."""
+    b, ptr = _field_args(field)
+    _check(load_library().ssfm_dft(plan, ptr, b, 1 if inverse else 0, _stream_ptr(field, stream)),
+           "ssfm_dft")
 
 
 def ssfm_adjoint(plan: int, field_in, grad, seed: int = 0, stream=None) -> None:
@@ -374,13 +386,19 @@ def ssfm_batch(links, fields, seeds, hip_device: int = 0, stream=None) -> None:
 class Plan:
     """A plan for one link on one device (see ``ssfm_plan``)."""
 
-    def __init__(self, link, device: Optional[int] = None):
+    def __init__(self, link, device: Optional[int] = None, arithmetic: str = "fp64"):
+        """``arithmetic``: "fp64" (the library's path) or "fp32" (the
+        FP32-arithmetic variant, SSFM_FLAG_FP32_ARITHMETIC; forward only)."""
         import torch
+        if arithmetic not in ("fp64", "fp32"):
+            raise ValueError("arithmetic must be 'fp64' or 'fp32'")
         self.link = link
+        self.arithmetic = arithmetic
         self.device = torch.cuda.current_device() if device is None else int(device)
         self.n_pol = int(link.n_pol)
         self.n_samples = int(link.n_samples)
-        self.handle = ssfm_plan(link, self.device)
+        self.handle = ssfm_plan(link, self.device,
+                                SSFM_FLAG_FP32_ARITHMETIC if arithmetic == "fp32" else 0)
 
     @property
     def info(self) -> dict:

@@ -1,4 +1,5 @@
-// Register/LDS Stockham FFT for gfx950, FP64 arithmetic.
+// Register/LDS Stockham FFT for gfx950 (FP64 arithmetic, or FP32 for the
+// FP32-arithmetic variant).
 //
 // Layout contract.  A length-M transform is carried by T = M/16 lanes; lane j
 // holds the 16 elements j + T*r (r = 0..15) of its transform in registers, in
@@ -19,10 +20,12 @@
 // Twiddles come from a table built in FP64 on the host: for each pass p >= 1
 // a block of ns(p) rows of radix(p) entries, row k holding
 // W_{ns R}^{k r} = exp(-2 pi i k r / (ns R)); the inverse transform uses their
-// conjugates.  All
-// arithmetic is FP64, so the coefficients of the linear operator carry no
-// FP32 rounding (a fixed rounding error in them would repeat identically at
-// every split step and grow linearly with the step count).
+// conjugates.  The transforms are templates on the complex type of the
+// registers: FP64 (cd) on the production path, so the coefficients of the
+// linear operator carry no FP32 rounding (a fixed rounding error in them would
+// repeat identically at every split step and grow linearly with the step
+// count), or FP32 (cf) for the FP32-arithmetic variant, whose coefficients are
+// the FP64 table values rounded to FP32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,29 +33,45 @@
 
 namespace ssfm {
 
-struct cd {
-  double re, im;
+// Complex value of real type R: FP64 (cd) on the default path, FP32 (cf) on
+// the FP32-arithmetic variant.
+template <typename R>
+struct cplx {
+  R re, im;
 };
+using cd = cplx<double>;
+using cf = cplx<float>;
 
-__device__ __forceinline__ cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cd operator-(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> cscale(cplx<R> a, R s) { return {a.re * s, a.im * s}; }
 // a * b
-__device__ __forceinline__ cd cmul(cd a, cd b) {
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
   return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
 }
 // a * conj(b)
-__device__ __forceinline__ cd cmulc(cd a, cd b) {
+template <typename R>
+__device__ __forceinline__ cplx<R> cmulc(cplx<R> a, cplx<R> b) {
   return {fma(a.re, b.re, a.im * b.im), fma(a.im, b.re, -a.re * b.im)};
 }
-template <bool CONJ>
-__device__ __forceinline__ cd cmul_t(cd a, cd b) {
+template <bool CONJ, typename R>
+__device__ __forceinline__ cplx<R> cmul_t(cplx<R> a, cplx<R> b) {
   return CONJ ? cmulc(a, b) : cmul(a, b);
 }
 // multiply by -i (forward) or +i (inverse): the exp(-+ i pi/2) rotation
-template <bool INV>
-__device__ __forceinline__ cd rot90(cd a) {
-  return INV ? cd{-a.im, a.re} : cd{a.im, -a.re};
+template <bool INV, typename R>
+__device__ __forceinline__ cplx<R> rot90(cplx<R> a) {
+  return INV ? cplx<R>{-a.im, a.re} : cplx<R>{a.im, -a.re};
+}
+// value conversions between the two precisions (identity for the same type)
+template <typename T, typename R>
+__device__ __forceinline__ T cconv(cplx<R> v) {
+  using U = decltype(T{}.re);
+  return {(U)v.re, (U)v.im};
 }
 
 // exp(-2 pi i k / 16) for the forward transform, conjugate for the inverse.
@@ -73,25 +92,25 @@ __device__ __forceinline__ cd w16() {
   return {re, INV ? sn : -sn};
 }
 
-template <bool INV, int K>
-__device__ __forceinline__ cd mul_w16(cd a) {
+template <bool INV, int K, typename R>
+__device__ __forceinline__ cplx<R> mul_w16(cplx<R> a) {
   if constexpr ((K & 15) == 0) return a;
   else if constexpr ((K & 15) == 4) return rot90<INV>(a);
-  else if constexpr ((K & 15) == 8) return cd{-a.re, -a.im};
+  else if constexpr ((K & 15) == 8) return cplx<R>{-a.re, -a.im};
   else if constexpr ((K & 15) == 12) return rot90<!INV>(a);
-  else return cmul(a, w16<INV, K>());
+  else return cmul(a, cconv<cplx<R>>(w16<INV, K>()));
 }
 
-template <bool INV>
-__device__ __forceinline__ void dft2(cd& a0, cd& a1) {
-  cd t = a0;
+template <bool INV, typename CT>
+__device__ __forceinline__ void dft2(CT& a0, CT& a1) {
+  CT t = a0;
   a0 = t + a1;
   a1 = t - a1;
 }
 
-template <bool INV>
-__device__ __forceinline__ void dft4(cd& a0, cd& a1, cd& a2, cd& a3) {
-  cd t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<INV>(a1 - a3);
+template <bool INV, typename CT>
+__device__ __forceinline__ void dft4(CT& a0, CT& a1, CT& a2, CT& a3) {
+  CT t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<INV>(a1 - a3);
   a0 = t0 + t2;
   a2 = t0 - t2;
   a1 = t1 + t3;
@@ -101,8 +120,8 @@ __device__ __forceinline__ void dft4(cd& a0, cd& a1, cd& a2, cd& a3) {
 // In-place DFT of length R on v[0..R-1], natural order in and out.
 // R = 8 and 16 use the 4 x 2 and 4 x 4 Cooley-Tukey splits with the
 // internal twiddles W_R^{b c}.
-template <int R, bool INV>
-__device__ __forceinline__ void dft(cd* v) {
+template <int R, bool INV, typename CT>
+__device__ __forceinline__ void dft(CT* v) {
   if constexpr (R == 2) {
     dft2<INV>(v[0], v[1]);
   } else if constexpr (R == 4) {
@@ -114,10 +133,10 @@ __device__ __forceinline__ void dft(cd* v) {
     v[3] = mul_w16<INV, 2>(v[3]);       // W8^1 = W16^2
     v[5] = mul_w16<INV, 4>(v[5]);       // W8^2
     v[7] = mul_w16<INV, 6>(v[7]);       // W8^3
-    cd x[8];
+    CT x[8];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      cd a = v[2 * c], b = v[2 * c + 1];
+      CT a = v[2 * c], b = v[2 * c + 1];
       dft2<INV>(a, b);
       x[c] = a;
       x[c + 4] = b;
@@ -139,10 +158,10 @@ __device__ __forceinline__ void dft(cd* v) {
     v[13] = mul_w16<INV, 3>(v[13]);
     v[14] = mul_w16<INV, 6>(v[14]);
     v[15] = mul_w16<INV, 9>(v[15]);
-    cd x[16];
+    CT x[16];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      cd a0 = v[4 * c], a1 = v[4 * c + 1], a2 = v[4 * c + 2], a3 = v[4 * c + 3];
+      CT a0 = v[4 * c], a1 = v[4 * c + 1], a2 = v[4 * c + 2], a3 = v[4 * c + 3];
       dft4<INV>(a0, a1, a2, a3);
       x[c] = a0;
       x[c + 4] = a1;
@@ -204,15 +223,19 @@ __device__ __forceinline__ void xsync() {
   else __syncthreads();
 }
 
-// LDS element conversions: FP64 values are held as cd or rounded to float2.
-__device__ __forceinline__ void lds_put(cd* p, cd v) { *p = v; }
-__device__ __forceinline__ void lds_put(float2* p, cd v) {
+// LDS element conversions: values are held as cd or rounded to float2.
+template <typename R>
+__device__ __forceinline__ void lds_put(cd* p, cplx<R> v) { *p = cconv<cd>(v); }
+template <typename R>
+__device__ __forceinline__ void lds_put(float2* p, cplx<R> v) {
   *p = make_float2((float)v.re, (float)v.im);
 }
-__device__ __forceinline__ cd lds_get(const cd* p) { return *p; }
-__device__ __forceinline__ cd lds_get(const float2* p) {
+template <typename CT>
+__device__ __forceinline__ CT lds_get(const cd* p) { return cconv<CT>(*p); }
+template <typename CT>
+__device__ __forceinline__ CT lds_get(const float2* p) {
   float2 v = *p;
-  return {(double)v.x, (double)v.y};
+  return cconv<CT>(cf{v.x, v.y});
 }
 
 // LDS slot of element i.  The first pass writes with a stride of 16
@@ -231,7 +254,7 @@ __device__ __forceinline__ int lds_slot(int i, int ls) {
 // runs many transforms keeps them in registers instead of reading the table
 // inside every transform (where the read would wait behind the lane's other
 // outstanding global loads).
-template <int M>
+template <int M, typename CT = cd>
 struct fft_twiddles {
   using S = fft_shape<M>;
   static constexpr int first(int P) {
@@ -240,7 +263,7 @@ struct fft_twiddles {
     return c;
   }
   static constexpr int count = first(S::passes);
-  cd w[count > 0 ? count : 1];
+  CT w[count > 0 ? count : 1];
 
   __device__ __forceinline__ void load(const cd* __restrict__ tw, int j) {
 #pragma unroll
@@ -248,7 +271,7 @@ struct fft_twiddles {
       const int R = S::radix(p), NS = S::ns(p);
 #pragma unroll
       for (int q = 0; q < 16 / R; ++q)
-        w[first(p) + q] = tw[S::tw_offset(p) + ((j + S::T * q) % NS) * R + 1];
+        w[first(p) + q] = cconv<CT>(tw[S::tw_offset(p) + ((j + S::T * q) % NS) * R + 1]);
     }
   }
 };
@@ -257,19 +280,19 @@ struct fft_twiddles {
 // the lane's preloaded set.  (Every level takes the twiddle source as a
 // restrict pointer: without it the compiler serialises the row pass's field
 // loads.)
-template <int M, int P>
-__device__ __forceinline__ cd pass_twiddle(const cd* __restrict__ tw, int jj, int) {
+template <int M, int P, typename CT>
+__device__ __forceinline__ CT pass_twiddle(const cd* __restrict__ tw, int jj, int) {
   using S = fft_shape<M>;
-  return tw[S::tw_offset(P) + (jj % S::ns(P)) * S::radix(P) + 1];
+  return cconv<CT>(tw[S::tw_offset(P) + (jj % S::ns(P)) * S::radix(P) + 1]);
 }
-template <int M, int P>
-__device__ __forceinline__ cd pass_twiddle(const fft_twiddles<M>* __restrict__ tw, int, int q) {
-  return tw->w[fft_twiddles<M>::first(P) + q];
+template <int M, int P, typename CT>
+__device__ __forceinline__ CT pass_twiddle(const fft_twiddles<M, CT>* __restrict__ tw, int, int q) {
+  return tw->w[fft_twiddles<M, CT>::first(P) + q];
 }
 
 // Read the inputs of pass P from LDS into the registers.
-template <int M, int P, int PAD, typename L>
-__device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, int j) {
+template <int M, int P, int PAD, typename L, typename CT>
+__device__ __forceinline__ void pass_load(CT (&reg)[16], const L* lds, int ls, int j) {
   using S = fft_shape<M>;
   constexpr int R = S::radix(P);
   constexpr int NB = 16 / R;
@@ -278,14 +301,14 @@ __device__ __forceinline__ void pass_load(cd (&reg)[16], const L* lds, int ls, i
   for (int q = 0; q < NB; ++q) {
     const int jj = j + T * q;
 #pragma unroll
-    for (int r = 0; r < R; ++r) reg[q + r * NB] = lds_get(lds + lds_slot<PAD>(jj + r * (M / R), ls));
+    for (int r = 0; r < R; ++r) reg[q + r * NB] = lds_get<CT>(lds + lds_slot<PAD>(jj + r * (M / R), ls));
   }
 }
 
 // Twiddle, butterfly and write of pass P.  DST_REG: the outputs stay in the
 // registers (last pass), otherwise they are written to LDS.
-template <int M, int P, bool INV, bool DST_REG, int PAD, typename L, typename TW>
-__device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int j,
+template <int M, int P, bool INV, bool DST_REG, int PAD, typename L, typename TW, typename CT>
+__device__ __forceinline__ void pass_compute(CT (&reg)[16], L* lds, int ls, int j,
                                              TW __restrict__ tw) {
   using S = fft_shape<M>;
   constexpr int R = S::radix(P);
@@ -295,7 +318,7 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int jj = j + T * q;
-    cd v[R];
+    CT v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = reg[q + r * NB];
     if constexpr (NS > 1) {
@@ -303,8 +326,8 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
       // block (row k, entry 1), powers by FP64 products (~r ulps of FP64, far
       // below the single-precision storage of the field; one load per
       // butterfly keeps the register footprint down)
-      const cd w = pass_twiddle<M, P>(tw, jj, q);
-      cd wr = w;
+      const CT w = pass_twiddle<M, P, CT>(tw, jj, q);
+      CT wr = w;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         v[r] = cmul_t<INV>(v[r], wr);
@@ -323,8 +346,8 @@ __device__ __forceinline__ void pass_compute(cd (&reg)[16], L* lds, int ls, int 
   }
 }
 
-template <int M, bool INV, int P, int NT, int PAD, bool WAVE, typename L, typename TW>
-__device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride, int ls,
+template <int M, bool INV, int P, int NT, int PAD, bool WAVE, typename L, typename TW, typename CT>
+__device__ __forceinline__ void fft_rest(CT (&reg)[NT][16], L* lds, int tstride, int ls,
                                          int j, TW __restrict__ tw) {
   using S = fft_shape<M>;
   if constexpr (P < S::passes) {
@@ -340,8 +363,8 @@ __device__ __forceinline__ void fft_rest(cd (&reg)[NT][16], L* lds, int tstride,
   }
 }
 
-template <int M, bool INV, int NT, int PAD, bool WAVE, typename L, typename TW>
-__device__ __forceinline__ void fft_multi_impl(cd (&reg)[NT][16], L* lds, int tstride, int ls,
+template <int M, bool INV, int NT, int PAD, bool WAVE, typename L, typename TW, typename CT>
+__device__ __forceinline__ void fft_multi_impl(CT (&reg)[NT][16], L* lds, int tstride, int ls,
                                                int j, TW __restrict__ tw) {
   using S = fft_shape<M>;
   if constexpr (S::passes == 1) {
@@ -365,22 +388,22 @@ __device__ __forceinline__ void fft_multi_impl(cd (&reg)[NT][16], L* lds, int ts
 // regions is in the calling wave (see xsync); otherwise the whole block must
 // call.  The pass twiddles come from the table tw, or from a lane's
 // preloaded fft_twiddles<M>.
-template <int M, bool INV, int NT, int PAD, bool WAVE, typename L>
-__device__ __forceinline__ void fft_multi(cd (&reg)[NT][16], L* lds, int tstride, int ls,
+template <int M, bool INV, int NT, int PAD, bool WAVE, typename L, typename CT>
+__device__ __forceinline__ void fft_multi(CT (&reg)[NT][16], L* lds, int tstride, int ls,
                                           int j, const cd* __restrict__ tw) {
   fft_multi_impl<M, INV, NT, PAD, WAVE>(reg, lds, tstride, ls, j, tw);
 }
 
-template <int M, bool INV, int PAD, bool WAVE, typename L>
-__device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
+template <int M, bool INV, int PAD, bool WAVE, typename L, typename CT>
+__device__ __forceinline__ void fft(CT (&reg)[16], L* lds, int ls, int j,
                                     const cd* __restrict__ tw) {
-  fft_multi_impl<M, INV, 1, PAD, WAVE>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j, tw);
+  fft_multi_impl<M, INV, 1, PAD, WAVE>(*reinterpret_cast<CT(*)[1][16]>(&reg), lds, 0, ls, j, tw);
 }
 
-template <int M, bool INV, int PAD, bool WAVE, typename L>
-__device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
-                                    const fft_twiddles<M>& tw) {
-  fft_multi_impl<M, INV, 1, PAD, WAVE>(*reinterpret_cast<cd(*)[1][16]>(&reg), lds, 0, ls, j,
+template <int M, bool INV, int PAD, bool WAVE, typename L, typename CT>
+__device__ __forceinline__ void fft(CT (&reg)[16], L* lds, int ls, int j,
+                                    const fft_twiddles<M, CT>& tw) {
+  fft_multi_impl<M, INV, 1, PAD, WAVE>(*reinterpret_cast<CT(*)[1][16]>(&reg), lds, 0, ls, j,
                                        &tw);
 }
 
@@ -388,29 +411,29 @@ __device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
 // registers when there are at most two of them (read right after the
 // kernel's field loads, so no transform waits on a table read behind other
 // loads), else the table.
-template <int M, bool PRE = (fft_twiddles<M>::count <= 2)>
+template <int M, typename CT = cd, bool PRE = (fft_twiddles<M, CT>::count <= 2)>
 struct lane_twiddles {
-  fft_twiddles<M> t;
+  fft_twiddles<M, CT> t;
   __device__ __forceinline__ lane_twiddles(const cd* __restrict__ tw, int j) { t.load(tw, j); }
   // Hide the values from the optimiser: what a transform computes from them
   // (the powers of the pass twiddle) is then formed again in the next one
   // instead of being kept in registers from the earlier transform.
   __device__ __forceinline__ void opaque() {
 #pragma unroll
-    for (int i = 0; i < fft_twiddles<M>::count; ++i)
+    for (int i = 0; i < fft_twiddles<M, CT>::count; ++i)
       asm volatile("" : "+v"(t.w[i].re), "+v"(t.w[i].im));
   }
 };
-template <int M>
-struct lane_twiddles<M, false> {
+template <int M, typename CT>
+struct lane_twiddles<M, CT, false> {
   const cd* tw;
   __device__ __forceinline__ lane_twiddles(const cd* __restrict__ table, int) : tw(table) {}
   __device__ __forceinline__ void opaque() {}
 };
 
-template <int M, bool INV, int PAD, bool WAVE, typename L, bool PRE>
-__device__ __forceinline__ void fft(cd (&reg)[16], L* lds, int ls, int j,
-                                    const lane_twiddles<M, PRE>& lt) {
+template <int M, bool INV, int PAD, bool WAVE, typename L, typename CT, bool PRE>
+__device__ __forceinline__ void fft(CT (&reg)[16], L* lds, int ls, int j,
+                                    const lane_twiddles<M, CT, PRE>& lt) {
   if constexpr (PRE) fft<M, INV, PAD, WAVE>(reg, lds, ls, j, lt.t);
   else fft<M, INV, PAD, WAVE>(reg, lds, ls, j, lt.tw);
 }

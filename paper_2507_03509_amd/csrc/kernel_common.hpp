@@ -7,11 +7,13 @@
 
 namespace ssfm {
 
-__device__ __forceinline__ cd load_c64(const float2* p) {
+template <typename CT = cd>
+__device__ __forceinline__ CT load_c64(const float2* p) {
   float2 v = *p;
-  return {(double)v.x, (double)v.y};
+  return cconv<CT>(cf{v.x, v.y});
 }
-__device__ __forceinline__ void store_c64(float2* p, cd v) {
+template <typename R>
+__device__ __forceinline__ void store_c64(float2* p, cplx<R> v) {
   *p = make_float2((float)v.re, (float)v.im);
 }
 // Strided access to the elements j + T r (r < 16) of a lane's column through
@@ -37,11 +39,13 @@ __device__ __forceinline__ float2 col_load_f2(const col_buf& b, int r) {
   return __builtin_bit_cast(
       float2, __builtin_amdgcn_raw_buffer_load_b64(b.rs, b.lane, (uint32_t)r * b.step, 0));
 }
-__device__ __forceinline__ cd col_load(const col_buf& b, int r) {
+template <typename CT = cd>
+__device__ __forceinline__ CT col_load(const col_buf& b, int r) {
   const float2 v = col_load_f2(b, r);
-  return {(double)v.x, (double)v.y};
+  return cconv<CT>(cf{v.x, v.y});
 }
-__device__ __forceinline__ void col_store(const col_buf& b, int r, cd v) {
+template <typename R>
+__device__ __forceinline__ void col_store(const col_buf& b, int r, cplx<R> v) {
   using raw64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(b.rs, 0, 0, 0));
   const float2 f = make_float2((float)v.re, (float)v.im);
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(raw64, f), b.rs, b.lane,
@@ -159,6 +163,28 @@ __device__ __forceinline__ double pair32_sum(double x) {
   const double lower = __builtin_bit_cast(double, ((uint64_t)rh[0] << 32) | rl[0]);
   const double upper = __builtin_bit_cast(double, ((uint64_t)rh[1] << 32) | rl[1]);
   return lower + upper;
+}
+// FP32 operand: through the FP64 sum (exact for two floats of similar size),
+// rounded once.  (A 32-bit v_permlane32_swap of one value was compiled as the
+// first result added to itself.)
+__device__ __forceinline__ float pair32_sum(float x) { return (float)pair32_sum((double)x); }
+
+// The FP32-arithmetic variant's nonlinear rotation: f(r, exp(i phi[r])) with
+// the FP32 sine and cosine of HIP's device library.
+template <typename F>
+__device__ __forceinline__ void for_each_phasor16(const float (&phi)[16], F&& f) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    float sn, cs;
+    sincosf(phi[r], &sn, &cs);
+    f(r, cf{cs, sn});
+  }
+}
+
+// |v|^2 in the arithmetic of v
+template <typename R>
+__device__ __forceinline__ R cnorm2(cplx<R> v) {
+  return fma(v.re, v.re, v.im * v.im);
 }
 
 // twiddle W_N^m from the two-level table (m < N): twA[a] = W_N^{a N2},

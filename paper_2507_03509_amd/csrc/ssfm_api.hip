@@ -210,7 +210,8 @@ int validate_link(const ssfm_link* l) {
   if (l->ase && !finite(l->edfa_nf_db)) return api_fail(SSFM_EINVAL, "edfa_nf_db must be finite");
   if (!isnan(l->carrier_hz) && (!finite(l->carrier_hz) || l->carrier_hz <= 0))
     return api_fail(SSFM_EINVAL, "carrier_hz must be NaN or finite and > 0");
-  if (l->flags != 0 || l->reserved != 0) return api_fail(SSFM_EINVAL, "flags and reserved must be 0");
+  if ((l->flags & ~SSFM_FLAG_FP32_ARITHMETIC) != 0 || l->reserved != 0)
+    return api_fail(SSFM_EINVAL, "flags may only hold SSFM_FLAG_FP32_ARITHMETIC; reserved must be 0");
   return SSFM_OK;
 }
 
@@ -825,7 +826,7 @@ int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out) {
   p->n = link->n_samples;
   p->steps = link->steps_per_span;
   p->spans = link->n_spans;
-  if (!ssfm::select_kernels(p->n, p->n_pol, p->ks)) {
+  if (!ssfm::select_kernels(p->n, p->n_pol, (link->flags & SSFM_FLAG_FP32_ARITHMETIC) != 0, p->ks)) {
     delete p;
     return api_fail(SSFM_EUNSUPPORTED, "no kernel for n_samples = %lld", (long long)link->n_samples);
   }
@@ -945,6 +946,56 @@ int ssfm_forward(ssfm_plan_t plan, void* field, int64_t batch, uint64_t seed, vo
   return ssfm_forward_spans(plan, field, batch, seed, 0, 0, plan->spans, stream);
 }
 
+int ssfm_dft(ssfm_plan_t plan, void* field, int64_t batch, int32_t inverse, void* stream) {
+  ssfm::api_clear_error();
+  int rc = check_call(plan, field, batch);
+  if (rc != SSFM_OK) return rc;
+  if (inverse != 0 && inverse != 1) return api_fail(SSFM_EINVAL, "inverse must be 0 or 1");
+  DeviceGuard guard(plan->device);
+  if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float2* f = static_cast<float2*>(field);
+  const ssfm::KernelSet& ks = plan->ks;
+  const double bytes = 2.0 * (double)batch * plan->n_pol * (double)plan->n * sizeof(float2);
+  hipError_t e;
+  if (ks.path == 1) {
+    if ((e = launch(plan, KIND_LDS, bytes, st,
+                    [&] { return ks.lds_dft[inverse](f, plan->tw_n, batch, st); })) != hipSuccess)
+      return api_fail_hip(e, "k1_dft launch");
+    return SSFM_OK;
+  }
+  const Shape4 shape = pick_shape(plan, batch);
+  int log2_n2 = 0;
+  while ((1 << log2_n2) < ks.n2) ++log2_n2;
+  ssfm::RowArgs ra{};
+  ra.field = f;
+  ra.H = plan->h_full;  // not read by the transform-only row passes
+  ra.tw = plan->tw2;
+  ra.twA = plan->twA;
+  ra.twB = plan->twB;
+  ra.n1 = ks.n1;
+  ra.log2_n2 = log2_n2;
+  ra.part = inverse ? ssfm::ROW_IFFT : ssfm::ROW_FFT;
+  ssfm::ColArgs ca{};
+  ca.field = f;
+  ca.tw1 = plan->tw1;
+  ca.n2 = ks.n2;
+  ca.n = plan->n;
+  const int64_t rows = batch * plan->n_pol * ks.n1;
+  auto col = [&](int mode) {
+    return launch(plan, KIND_COL, bytes, st, [&] { return shape.cols->col[mode](ca, batch, st); });
+  };
+  auto row = [&] { return launch(plan, KIND_ROW, bytes, st, [&] { return shape.row(ra, rows, st); }); };
+  if (!inverse) {
+    if ((e = col(ssfm::MODE_FIRST)) != hipSuccess) return api_fail_hip(e, "k3 launch (dft)");
+    if ((e = row()) != hipSuccess) return api_fail_hip(e, "k2 launch (dft)");
+  } else {
+    if ((e = row()) != hipSuccess) return api_fail_hip(e, "k2 launch (dft)");
+    if ((e = col(ssfm::MODE_IFFT)) != hipSuccess) return api_fail_hip(e, "k3 launch (dft)");
+  }
+  return SSFM_OK;
+}
+
 int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t batch,
                  uint64_t seed, void* stream) {
   ssfm::api_clear_error();
@@ -954,6 +1005,8 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
   if (((uintptr_t)grad & 7u) != 0) return api_fail(SSFM_EINVAL, "grad must be 8-byte aligned");
   if (plan->ks.path != 2)
     return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint needs n_samples >= 2^14 (four-step path)");
+  if (plan->ks.fp32)
+    return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint: no adjoint for the FP32-arithmetic variant");
   DeviceGuard guard(plan->device);
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -985,6 +1038,8 @@ int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad, int
   if (((uintptr_t)grad & 7u) != 0) return api_fail(SSFM_EINVAL, "grad must be 8-byte aligned");
   if (plan->ks.path != 2)
     return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint_noalloc needs n_samples >= 2^14 (four-step path)");
+  if (plan->ks.fp32)
+    return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint_noalloc: no adjoint for the FP32-arithmetic variant");
   if (plan->profiling)
     return api_fail(SSFM_EINVAL, "ssfm_adjoint_noalloc: a profiling window is open on the plan "
                                  "(its per-launch events would be created here)");

@@ -14,7 +14,13 @@ enum { MODE_FIRST = 0,      // time -> mixed domain (start of the link)
        MODE_EDFA = 2,       // mixed -> time, amplifier + ASE, time -> mixed
        MODE_LAST = 3,       // mixed -> time, amplifier + ASE (end of the link)
        MODE_NL_STORE = 4,   // MODE_NL, also storing the nonlinear step's input
-       N_MODES = 5 };
+       MODE_IFFT = 5,       // mixed -> time only (the transform alone, ssfm_dft)
+       N_MODES = 6 };
+
+// row-pass variants: the linear step, or one of its two transforms alone
+enum { ROW_STEP = 0,        // twiddle, row FFT, x H, row IFFT, conj twiddle
+       ROW_FFT = 1,         // twiddle, row FFT (ssfm_dft forward)
+       ROW_IFFT = 2 };      // row IFFT, conj twiddle (ssfm_dft inverse)
 
 struct RowArgs {
   float2* field;
@@ -25,6 +31,7 @@ struct RowArgs {
   int n1;
   int log2_n2;
   int conj_h;        // 1: multiply by conj(H) (adjoint / inverse linear step)
+  int part;          // ROW_STEP, ROW_FFT or ROW_IFFT
 };
 
 struct ColArgs {
@@ -93,6 +100,7 @@ struct AdjStoredArgs {
 using RowLaunch = hipError_t (*)(const RowArgs&, int64_t, hipStream_t);
 using ColLaunch = hipError_t (*)(const ColArgs&, int64_t, hipStream_t);
 using LdsLaunch = hipError_t (*)(const LdsArgs&, int64_t, hipStream_t);
+using LdsDftLaunch = hipError_t (*)(float2*, const cd*, int64_t, hipStream_t);
 using AdjLaunch = hipError_t (*)(const AdjArgs&, hipStream_t);
 using AdjStoredLaunch = hipError_t (*)(const AdjStoredArgs&, int64_t, hipStream_t);
 
@@ -104,8 +112,10 @@ struct FourStepKernels {
 
 struct KernelSet {
   int path = 0;  // 1 = LDS-resident, 2 = four-step
+  bool fp32 = false;  // FP32-arithmetic variant (no adjoint kernels)
   int n1 = 0, n2 = 0;
   LdsLaunch lds = nullptr;
+  LdsDftLaunch lds_dft[2] = {nullptr, nullptr};  // the LDS-resident transform: forward, inverse
   RowLaunch row_wide = nullptr, row_narrow = nullptr;
   int rows_wide = 0, rows_narrow = 0;  // rows per workgroup
   // column tiles: narrow (2 columns) and wide (8, or 4 at N1 = 512)
@@ -116,9 +126,10 @@ struct KernelSet {
   hipError_t prepare = hipSuccess;
 };
 
-// Pick the kernel instantiations for n samples per polarisation.  Returns
-// false if no instantiation exists for that size.
-bool select_kernels(int64_t n, int n_pol, KernelSet& ks);
+// Pick the kernel instantiations for n samples per polarisation, FP64 or
+// (fp32) FP32 arithmetic.  Returns false if no instantiation exists for that
+// size.
+bool select_kernels(int64_t n, int n_pol, bool fp32, KernelSet& ks);
 
 // Fill ks.adj for the four-step column length n1 (leaves it empty if there is
 // no adjoint instantiation for that length).

@@ -26,6 +26,8 @@
 // position k1 N2 + k2 (transposed), where the dispersion table is laid out in
 // the same order.  Between passes the field sits in HBM in the mixed
 // (k1, n2) domain, so a split step costs exactly two read+write sweeps.
+#include <type_traits>
+
 #include "fft_dev.hpp"
 #include "kernel_common.hpp"
 #include "philox_dev.hpp"
@@ -36,7 +38,7 @@ namespace ssfm {
 // ---------------------------------------------------------------------------
 // K2: rows of length N2 (contiguous), WG lanes, FP32 LDS exchange.
 // ---------------------------------------------------------------------------
-template <int N2, int WG, typename L, bool CONJ>
+template <int N2, int WG, typename L, bool CONJ, typename R, int PART = ROW_STEP>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void k2_rows(float2* __restrict__ field, const cd* __restrict__ H,
                                               const cd* __restrict__ tw,
                                               const cd* __restrict__ twA,
@@ -51,29 +53,33 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const int k1 = (int)(row & (n1 - 1));  // n1 is a power of two
   float2* rp = field + row * N2;
   L* mylds = lds2 + lr * (N2 + N2 / 16);  // padded row: stride = 16 mod 32 slots
-  cd reg[16];
+  using CT = cplx<R>;
+  CT reg[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) reg[r] = load_c64(rp + j + T * r);
-  const lane_twiddles<N2> ltw(tw, j);
+  for (int r = 0; r < 16; ++r) reg[r] = load_c64<CT>(rp + j + T * r);
+  const lane_twiddles<N2, CT> ltw(tw, j);
   // four-step twiddle W_N^{n2 k1} on n2 = j + T r: W_N^{k1 j} (W_N^{k1 T})^r
-  const cd w0 = four_step_twiddle(twA, twB, k1 * j, log2_n2, N2);
-  const cd wstep = four_step_twiddle(twA, twB, k1 * T, log2_n2, N2);
-  {
-    cd w = w0;
+  const CT w0 = cconv<CT>(four_step_twiddle(twA, twB, k1 * j, log2_n2, N2));
+  const CT wstep = cconv<CT>(four_step_twiddle(twA, twB, k1 * T, log2_n2, N2));
+  if constexpr (PART != ROW_IFFT) {
+    CT w = w0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       reg[r] = cmul(reg[r], w);
       if (r < 15) w = cmul(w, wstep);
     }
+    fft<N2, false, true, true>(reg, mylds, 1, j, ltw);  // one wave per row
   }
-  fft<N2, false, true, true>(reg, mylds, 1, j, ltw);  // one wave per row
-  const cd* hp = H + (int64_t)k1 * N2;
-  // CONJ: conj(H), the adjoint (and inverse) of the unitary linear step
+  if constexpr (PART == ROW_STEP) {
+    const cd* hp = H + (int64_t)k1 * N2;
+    // CONJ: conj(H), the adjoint (and inverse) of the unitary linear step.
+    // The dispersion multiply is FP64 in both arithmetic variants.
 #pragma unroll
-  for (int r = 0; r < 16; ++r) reg[r] = cmul_t<CONJ>(reg[r], hp[j + T * r]);
-  fft<N2, true, true, true>(reg, mylds, 1, j, ltw);
-  {
-    cd w = w0;
+    for (int r = 0; r < 16; ++r) reg[r] = cconv<CT>(cmul_t<CONJ>(cconv<cd>(reg[r]), hp[j + T * r]));
+  }
+  if constexpr (PART != ROW_FFT) {
+    fft<N2, true, true, true>(reg, mylds, 1, j, ltw);
+    CT w = w0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       reg[r] = cmulc(reg[r], w);
@@ -89,8 +95,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 // ---------------------------------------------------------------------------
 
 
-template <int N1, int C, int P, int MODE, typename L>
+template <int N1, int C, int P, int MODE, typename L, typename R>
 __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_eu(2, 2))) void k3_cols(ColArgs a) {
+  using CT = cplx<R>;
   constexpr int T = N1 / 16;
   extern __shared__ __align__(16) unsigned char lds3_raw[];
   L* lds3 = reinterpret_cast<L*>(lds3_raw);
@@ -131,10 +138,10 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
   const uint32_t step = (uint32_t)(T * a.n2) * 8u;
   const col_buf fb = make_col_buf(a.field + b * P * a.n + col0, tile_bytes, lane_off, step);
   L* mylds = lds3 + p * (N1 * C) + c;
-  cd reg[16];
+  CT reg[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) reg[r] = col_load(fb, r);
-  const lane_twiddles<N1> ltw(a.tw1, j);
+  for (int r = 0; r < 16; ++r) reg[r] = col_load<CT>(fb, r);
+  const lane_twiddles<N1, CT> ltw(a.tw1, j);
 
   if constexpr (MODE != MODE_FIRST) {
     // mixed (k1, n2) domain -> time: inverse column FFT
@@ -146,38 +153,36 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
       for (int r = 0; r < 16; ++r) col_store(sb, r, reg[r]);
     }
     if constexpr (MODE == MODE_NL || MODE == MODE_NL_STORE) {
+      const R kappa = (R)a.kappa;
       if constexpr (PAIR) {
         // |a_x|^2 + |a_y|^2 from the lane pair, added x + y on both lanes,
         // so both rotate by the same phase
-        double phi[16];
+        R phi[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          phi[r] = a.kappa * pair32_sum(fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im));
-        for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
+        for (int r = 0; r < 16; ++r) phi[r] = kappa * pair32_sum(cnorm2(reg[r]));
+        for_each_phasor16(phi, [&](int r, CT e) { reg[r] = cmul(reg[r], e); });
       } else if constexpr (P == 2) {
         // exchange |a_p|^2 with the lane of the other polarisation (the sum
         // is formed x + y on both lanes, so both rotate by the same phase)
-        double* pbuf = reinterpret_cast<double*>(lds3_raw);
+        R* pbuf = reinterpret_cast<R*>(lds3_raw);
         __syncthreads();  // the inverse FFT's LDS reads are done
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          pbuf[p * (N1 * C) + (j + T * r) * C + c] = fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im);
+        for (int r = 0; r < 16; ++r) pbuf[p * (N1 * C) + (j + T * r) * C + c] = cnorm2(reg[r]);
         __syncthreads();
-        double phi[16];
+        R phi[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int i = (j + T * r) * C + c;
-          phi[r] = a.kappa * (pbuf[i] + pbuf[N1 * C + i]);
+          phi[r] = kappa * (pbuf[i] + pbuf[N1 * C + i]);
         }
-        for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
+        for_each_phasor16(phi, [&](int r, CT e) { reg[r] = cmul(reg[r], e); });
       } else {
-        double phi[16];
+        R phi[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          phi[r] = a.kappa * fma(reg[r].re, reg[r].re, reg[r].im * reg[r].im);
-        for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
+        for (int r = 0; r < 16; ++r) phi[r] = kappa * cnorm2(reg[r]);
+        for_each_phasor16(phi, [&](int r, CT e) { reg[r] = cmul(reg[r], e); });
       }
-    } else {
+    } else if constexpr (MODE == MODE_EDFA || MODE == MODE_LAST) {
       // amplifier: a <- gspan a + ASE(t), t = n1 N2 + n2.  The noise is drawn
       // in a rolled loop into this lane's own LDS slots and added back in an
       // unrolled one, so the field registers are never indexed at run time.
@@ -203,17 +208,17 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        cd v = cscale(reg[r], a.gspan);
+        cd v = cscale(cconv<cd>(reg[r]), a.gspan);
         if (noisy) {
           const float2 g = nbuf[(j + T * r) * C];
           v.re = fma(a.sigma_h, (double)g.x, v.re);
           v.im = fma(a.sigma_h, (double)g.y, v.im);
         }
-        reg[r] = round_c64(v);
+        reg[r] = cconv<CT>(round_c64(v));
       }
     }
   }
-  if constexpr (MODE != MODE_LAST) {
+  if constexpr (MODE != MODE_LAST && MODE != MODE_IFFT) {
     // time -> mixed domain: column FFT
     fft<N1, false, false, false>(reg, mylds, C, j, ltw);
   }
@@ -227,8 +232,9 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
 // ---------------------------------------------------------------------------
 
 
-template <int N, int P, typename L>
+template <int N, int P, typename L, typename R>
 __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
+  using CT = cplx<R>;
   constexpr int T = N / 16;
   extern __shared__ __align__(16) unsigned char lds1_raw[];
   L* lds1 = reinterpret_cast<L*>(lds1_raw);
@@ -236,11 +242,11 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
   const int jj = threadIdx.x;  // the block is exactly T lanes
   const int64_t b = blockIdx.x;
   float2* fp = a.field + b * P * N;
-  cd reg[P][16];
+  CT reg[P][16];
 #pragma unroll
   for (int q = 0; q < P; ++q)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) reg[q][r] = load_c64(fp + q * N + jj + T * r);
+    for (int r = 0; r < 16; ++r) reg[q][r] = load_c64<CT>(fp + q * N + jj + T * r);
 
   const uint64_t key0 = a.seeds ? a.seeds[b] : a.seed;
   const uint64_t rkey = a.seeds ? 0ull : (a.realization0 + (uint64_t)b) * 65536ull;
@@ -248,27 +254,28 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
     for (int i = 0; i <= a.steps; ++i) {
       if (i > 0) {
         // nonlinear phase of step i-1
-        const double kap = a.kappa[i - 1];
-        double phi[16];
+        const R kap = (R)a.kappa[i - 1];
+        R phi[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          double pw = 0.0;
+          R pw = 0;
 #pragma unroll
           for (int q = 0; q < P; ++q) pw = fma(reg[q][r].re, reg[q][r].re, fma(reg[q][r].im, reg[q][r].im, pw));
           phi[r] = kap * pw;
         }
-        for_each_phasor16(phi, [&](int r, cd rot) {
+        for_each_phasor16(phi, [&](int r, CT rot) {
 #pragma unroll
           for (int q = 0; q < P; ++q) reg[q][r] = cmul(reg[q][r], rot);
         });
       }
       const cd* h = (i == 0 || i == a.steps) ? a.h_half : a.h_full;
       fft_multi<N, false, P, true, false>(reg, lds1, N + N / 16, 1, jj, a.tw);
+      // the dispersion multiply is FP64 in both arithmetic variants
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const cd hv = h[jj + T * r];
 #pragma unroll
-        for (int q = 0; q < P; ++q) reg[q][r] = cmul(reg[q][r], hv);
+        for (int q = 0; q < P; ++q) reg[q][r] = cconv<CT>(cmul(cconv<cd>(reg[q][r]), hv));
       }
       fft_multi<N, true, P, true, false>(reg, lds1, N + N / 16, 1, jj, a.tw);
     }
@@ -288,13 +295,13 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
     for (int r = 0; r < 16; ++r) {
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        reg[q][r] = cscale(reg[q][r], a.gspan);
+        cd v = cscale(cconv<cd>(reg[q][r]), a.gspan);
         if (noisy) {
           const float2 g = nbuf[q * N + jj + T * r];
-          reg[q][r].re = fma(a.sigma_h, (double)g.x, reg[q][r].re);
-          reg[q][r].im = fma(a.sigma_h, (double)g.y, reg[q][r].im);
+          v.re = fma(a.sigma_h, (double)g.x, v.re);
+          v.im = fma(a.sigma_h, (double)g.y, v.im);
         }
-        reg[q][r] = round_c64(reg[q][r]);
+        reg[q][r] = cconv<CT>(round_c64(v));
       }
     }
   }
@@ -304,33 +311,65 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
     for (int r = 0; r < 16; ++r) store_c64(fp + q * N + jj + T * r, reg[q][r]);
 }
 
+// The LDS-resident transform alone (ssfm_dft): k1_lds's load, one FFT (or
+// IFFT) of every polarisation, store.
+template <int N, int P, typename L, typename R, bool INV>
+__global__ __launch_bounds__(N / 16) void k1_dft(float2* field, const cd* tw) {
+  using CT = cplx<R>;
+  constexpr int T = N / 16;
+  extern __shared__ __align__(16) unsigned char lds1d_raw[];
+  L* lds1 = reinterpret_cast<L*>(lds1d_raw);
+  const int jj = threadIdx.x;
+  float2* fp = field + (int64_t)blockIdx.x * P * N;
+  CT reg[P][16];
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) reg[q][r] = load_c64<CT>(fp + q * N + jj + T * r);
+  fft_multi<N, INV, P, true, false>(reg, lds1, N + N / 16, 1, jj, tw);
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) store_c64(fp + q * N + jj + T * r, reg[q][r]);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (host side): one function per instantiation, selected at plan time.
 // ---------------------------------------------------------------------------
-template <int N2, int WG, typename L>
+template <int N2, int WG, typename L, typename R>
 static hipError_t launch_k2(const RowArgs& a, int64_t rows, hipStream_t st) {
   constexpr int T = N2 / 16;
   constexpr int RPW = WG / T;
   const size_t lds = (size_t)RPW * (N2 + N2 / 16) * sizeof(L);
-  if (a.conj_h)
-    hipLaunchKernelGGL((k2_rows<N2, WG, L, true>), dim3((unsigned)(rows / RPW)), dim3(WG), lds,
-                       st, a.field, a.H, a.tw, a.twA, a.twB, a.n1, a.log2_n2);
+  const dim3 grid((unsigned)(rows / RPW));
+  if (a.part == ROW_FFT)
+    hipLaunchKernelGGL((k2_rows<N2, WG, L, false, R, ROW_FFT>), grid, dim3(WG), lds, st, a.field,
+                       a.H, a.tw, a.twA, a.twB, a.n1, a.log2_n2);
+  else if (a.part == ROW_IFFT)
+    hipLaunchKernelGGL((k2_rows<N2, WG, L, false, R, ROW_IFFT>), grid, dim3(WG), lds, st,
+                       a.field, a.H, a.tw, a.twA, a.twB, a.n1, a.log2_n2);
+  else if (a.conj_h)
+    hipLaunchKernelGGL((k2_rows<N2, WG, L, true, R>), grid, dim3(WG), lds, st, a.field, a.H, a.tw,
+                       a.twA, a.twB, a.n1, a.log2_n2);
   else
-    hipLaunchKernelGGL((k2_rows<N2, WG, L, false>), dim3((unsigned)(rows / RPW)), dim3(WG), lds,
-                       st, a.field, a.H, a.tw, a.twA, a.twB, a.n1, a.log2_n2);
+    hipLaunchKernelGGL((k2_rows<N2, WG, L, false, R>), grid, dim3(WG), lds, st, a.field, a.H,
+                       a.tw, a.twA, a.twB, a.n1, a.log2_n2);
   return hipGetLastError();
 }
 
-template <int N2, int WG, typename L>
+template <int N2, int WG, typename L, typename R>
 static hipError_t prepare_k2() {
   constexpr int T = N2 / 16;
   const size_t lds = (size_t)(WG / T) * (N2 + N2 / 16) * sizeof(L);
   if (lds <= 65536) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_rows<N2, WG, L, false>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_rows<N2, WG, L, true>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  for (const void* k : {reinterpret_cast<const void*>(&k2_rows<N2, WG, L, false, R>),
+                        reinterpret_cast<const void*>(&k2_rows<N2, WG, L, true, R>),
+                        reinterpret_cast<const void*>(&k2_rows<N2, WG, L, false, R, ROW_FFT>),
+                        reinterpret_cast<const void*>(&k2_rows<N2, WG, L, false, R, ROW_IFFT>)}) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int N1, int C, int P, int MODE, typename L>
@@ -340,12 +379,12 @@ constexpr size_t k3_lds_bytes() {
   return (size_t)P * C * N1 * (sizeof(L) > 8 ? sizeof(L) : 8);
 }
 
-template <int N1, int C, int P, int MODE, typename L>
+template <int N1, int C, int P, int MODE, typename L, typename R>
 static hipError_t launch_k3(const ColArgs& a, int64_t batch, hipStream_t st) {
   constexpr int T = N1 / 16;
   const unsigned blocks = (unsigned)(batch * (a.n2 / C));
   const size_t lds = k3_lds_bytes<N1, C, P, MODE, L>();
-  hipLaunchKernelGGL((k3_cols<N1, C, P, MODE, L>), dim3(blocks), dim3(P * C * T), lds, st, a);
+  hipLaunchKernelGGL((k3_cols<N1, C, P, MODE, L, R>), dim3(blocks), dim3(P * C * T), lds, st, a);
   return hipGetLastError();
 }
 
@@ -354,28 +393,40 @@ constexpr size_t k1_lds_bytes() {
   return (size_t)P * (N + N / 16) * sizeof(L);
 }
 
-template <int N, int P, typename L>
+template <int N, int P, typename L, typename R>
 static hipError_t launch_k1(const LdsArgs& a, int64_t batch, hipStream_t st) {
   constexpr int T = N / 16;
   const size_t lds = k1_lds_bytes<N, P, L>();
-  hipLaunchKernelGGL((k1_lds<N, P, L>), dim3((unsigned)batch), dim3(T), lds, st, a);
+  hipLaunchKernelGGL((k1_lds<N, P, L, R>), dim3((unsigned)batch), dim3(T), lds, st, a);
   return hipGetLastError();
 }
 
-template <int N, int P, typename L>
+template <int N, int P, typename L, typename R, bool INV>
+static hipError_t launch_k1_dft(float2* field, const cd* tw, int64_t batch, hipStream_t st) {
+  constexpr int T = N / 16;
+  const size_t lds = k1_lds_bytes<N, P, L>();
+  hipLaunchKernelGGL((k1_dft<N, P, L, R, INV>), dim3((unsigned)batch), dim3(T), lds, st, field, tw);
+  return hipGetLastError();
+}
+
+template <int N, int P, typename L, typename R>
 static hipError_t prepare_k1() {
   const size_t lds = k1_lds_bytes<N, P, L>();
-  if (lds > 65536)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k1_lds<N, P, L>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds <= 65536) return hipSuccess;
+  for (const void* k : {reinterpret_cast<const void*>(&k1_lds<N, P, L, R>),
+                        reinterpret_cast<const void*>(&k1_dft<N, P, L, R, false>),
+                        reinterpret_cast<const void*>(&k1_dft<N, P, L, R, true>)}) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
-template <int N1, int C, int P, int MODE, typename L>
+template <int N1, int C, int P, int MODE, typename L, typename R>
 static hipError_t prepare_k3_one() {
   const size_t lds = k3_lds_bytes<N1, C, P, MODE, L>();
   if (lds > 65536)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_cols<N1, C, P, MODE, L>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_cols<N1, C, P, MODE, L, R>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   return hipSuccess;
 }
@@ -388,47 +439,86 @@ static int log2i(int64_t v) {
   return l;
 }
 
-template <int N1, int C, int P, typename L>
+// The FP32-arithmetic variant has no nonlinear-step store (no adjoint).
+template <int N1, int C, int P, typename L, typename R>
 static void fill_k3(FourStepKernels& k) {
-  k.col[MODE_FIRST] = &launch_k3<N1, C, P, MODE_FIRST, L>;
-  k.col[MODE_NL] = &launch_k3<N1, C, P, MODE_NL, L>;
-  k.col[MODE_EDFA] = &launch_k3<N1, C, P, MODE_EDFA, L>;
-  k.col[MODE_LAST] = &launch_k3<N1, C, P, MODE_LAST, L>;
-  k.col[MODE_NL_STORE] = &launch_k3<N1, C, P, MODE_NL_STORE, L>;
+  constexpr bool F64 = sizeof(R) == 8;
+  k.col[MODE_FIRST] = &launch_k3<N1, C, P, MODE_FIRST, L, R>;
+  k.col[MODE_NL] = &launch_k3<N1, C, P, MODE_NL, L, R>;
+  k.col[MODE_EDFA] = &launch_k3<N1, C, P, MODE_EDFA, L, R>;
+  k.col[MODE_LAST] = &launch_k3<N1, C, P, MODE_LAST, L, R>;
+  k.col[MODE_IFFT] = &launch_k3<N1, C, P, MODE_IFFT, L, R>;
+  if constexpr (F64) k.col[MODE_NL_STORE] = &launch_k3<N1, C, P, MODE_NL_STORE, L, R>;
   k.columns = C;
-  k.prepare_status = prepare_k3_one<N1, C, P, MODE_FIRST, L>();
-  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_NL, L>();
-  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_EDFA, L>();
-  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_LAST, L>();
-  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_NL_STORE, L>();
+  k.prepare_status = prepare_k3_one<N1, C, P, MODE_FIRST, L, R>();
+  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_NL, L, R>();
+  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_EDFA, L, R>();
+  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_LAST, L, R>();
+  if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_IFFT, L, R>();
+  if constexpr (F64)
+    if (k.prepare_status == hipSuccess) k.prepare_status = prepare_k3_one<N1, C, P, MODE_NL_STORE, L, R>();
 }
 
-template <int N1, int P>
+// FFT exchanges in FP64 LDS (FP32 for the FP32 variant), 64 KB per workgroup
+// for the wide FP64 tiles: 8 (4 at N1 = 512) adjacent columns, 64/32-byte row
+// segments; narrow tiles: 2 columns, for batches too small to fill the chip
+template <int N1, int P, typename R>
 static void fill_cols(KernelSet& ks) {
-  // FFT exchanges in FP64 LDS, 64 KB per workgroup for the wide tiles: 8 (4 at
-  // N1 = 512) adjacent columns, 64/32-byte row segments; narrow tiles: 2
-  // columns, for batches too small to fill the chip
-  fill_k3<N1, N1 == 512 ? 4 : 8, P, cd>(ks.wide);
-  fill_k3<N1, 2, P, cd>(ks.narrow);
+  using L = std::conditional_t<sizeof(R) == 8, cd, float2>;
+  fill_k3<N1, N1 == 512 ? 4 : 8, P, L, R>(ks.wide);
+  fill_k3<N1, 2, P, L, R>(ks.narrow);
 }
 
-bool select_kernels(int64_t n, int n_pol, KernelSet& ks) {
+template <int N2, typename R>
+static hipError_t fill_rows(KernelSet& ks) {
+  using L = std::conditional_t<sizeof(R) == 8, cd, float2>;
+  constexpr int T = N2 / 16;
+  ks.row_wide = &launch_k2<N2, 256, L, R>;
+  ks.row_narrow = &launch_k2<N2, 64, L, R>;
+  ks.rows_narrow = 64 / T;
+  ks.rows_wide = 256 / T;
+  hipError_t e = prepare_k2<N2, 256, L, R>();
+  if (e == hipSuccess) e = prepare_k2<N2, 64, L, R>();
+  return e;
+}
+
+template <int N, typename R>
+static void fill_lds(KernelSet& ks, int n_pol) {
+  // FP64 LDS exchange where the padded field fits in 160 KB (every one-
+  // polarisation length, two polarisations up to 4096), else FP32; the FP32
+  // variant always exchanges FP32
+  constexpr bool F64 = sizeof(R) == 8;
+  using L1 = std::conditional_t<F64, cd, float2>;
+  using L2 = std::conditional_t<F64 && N <= 4096, cd, float2>;
+  if (n_pol == 1) {
+    ks.lds = &launch_k1<N, 1, L1, R>;
+    ks.lds_dft[0] = &launch_k1_dft<N, 1, L1, R, false>;
+    ks.lds_dft[1] = &launch_k1_dft<N, 1, L1, R, true>;
+    ks.prepare = prepare_k1<N, 1, L1, R>();
+  } else {
+    ks.lds = &launch_k1<N, 2, L2, R>;
+    ks.lds_dft[0] = &launch_k1_dft<N, 2, L2, R, false>;
+    ks.lds_dft[1] = &launch_k1_dft<N, 2, L2, R, true>;
+    ks.prepare = prepare_k1<N, 2, L2, R>();
+  }
+}
+
+template <typename R>
+static bool select_kernels_t(int64_t n, int n_pol, KernelSet& ks) {
   const int l = log2i(n);
-  ks = KernelSet{};
   if (l <= 13) {
     ks.path = 1;
-// FP64 LDS exchange where the padded field fits in 160 KB, else FP32
-#define K1CASE(LN, L2)                                                                          \
-  case LN:                                                                                      \
-    if (n_pol == 1) { ks.lds = &launch_k1<(1 << LN), 1, cd>; ks.prepare = prepare_k1<(1 << LN), 1, cd>(); } \
-    else { ks.lds = &launch_k1<(1 << LN), 2, L2>; ks.prepare = prepare_k1<(1 << LN), 2, L2>(); } \
-    return true;
     switch (l) {
-      K1CASE(6, cd) K1CASE(7, cd) K1CASE(8, cd) K1CASE(9, cd) K1CASE(10, cd) K1CASE(11, cd)
-      K1CASE(12, cd) K1CASE(13, float2)
+      case 6: fill_lds<64, R>(ks, n_pol); return true;
+      case 7: fill_lds<128, R>(ks, n_pol); return true;
+      case 8: fill_lds<256, R>(ks, n_pol); return true;
+      case 9: fill_lds<512, R>(ks, n_pol); return true;
+      case 10: fill_lds<1024, R>(ks, n_pol); return true;
+      case 11: fill_lds<2048, R>(ks, n_pol); return true;
+      case 12: fill_lds<4096, R>(ks, n_pol); return true;
+      case 13: fill_lds<8192, R>(ks, n_pol); return true;
       default: return false;
     }
-#undef K1CASE
   }
   ks.path = 2;
   const int l1 = l / 2;
@@ -436,31 +526,37 @@ bool select_kernels(int64_t n, int n_pol, KernelSet& ks) {
   ks.n2 = (int)(n >> l1);
   hipError_t pr = hipSuccess;
   switch (ks.n2) {
-    case 128: ks.row_wide = &launch_k2<128, 256, cd>; ks.row_narrow = &launch_k2<128, 64, cd>; ks.rows_narrow = 64 / 8; ks.rows_wide = 256 / 8; pr = prepare_k2<128, 256, cd>(); break;
-    case 256: ks.row_wide = &launch_k2<256, 256, cd>; ks.row_narrow = &launch_k2<256, 64, cd>; ks.rows_narrow = 64 / 16; ks.rows_wide = 256 / 16; pr = prepare_k2<256, 256, cd>(); break;
-    case 512: ks.row_wide = &launch_k2<512, 256, cd>; ks.row_narrow = &launch_k2<512, 64, cd>; ks.rows_narrow = 64 / 32; ks.rows_wide = 256 / 32; pr = prepare_k2<512, 256, cd>(); break;
+    case 128: pr = fill_rows<128, R>(ks); break;
+    case 256: pr = fill_rows<256, R>(ks); break;
+    case 512: pr = fill_rows<512, R>(ks); break;
     default: return false;
   }
   if (pr != hipSuccess) ks.prepare = pr;
   switch (ks.n1) {
     case 128:
-      if (n_pol == 1) { fill_cols<128, 1>(ks); }
-      else { fill_cols<128, 2>(ks); }
+      if (n_pol == 1) { fill_cols<128, 1, R>(ks); }
+      else { fill_cols<128, 2, R>(ks); }
       break;
     case 256:
-      if (n_pol == 1) { fill_cols<256, 1>(ks); }
-      else { fill_cols<256, 2>(ks); }
+      if (n_pol == 1) { fill_cols<256, 1, R>(ks); }
+      else { fill_cols<256, 2, R>(ks); }
       break;
     case 512:
-      if (n_pol == 1) { fill_cols<512, 1>(ks); }
-      else { fill_cols<512, 2>(ks); }
+      if (n_pol == 1) { fill_cols<512, 1, R>(ks); }
+      else { fill_cols<512, 2, R>(ks); }
       break;
     default: return false;
   }
   for (const FourStepKernels* k : {&ks.wide, &ks.narrow})
     if (k->prepare_status != hipSuccess) ks.prepare = k->prepare_status;
-  select_adjoint_kernels(ks.n1, n_pol, ks);
+  if constexpr (sizeof(R) == 8) select_adjoint_kernels(ks.n1, n_pol, ks);
   return true;
+}
+
+bool select_kernels(int64_t n, int n_pol, bool fp32, KernelSet& ks) {
+  ks = KernelSet{};
+  ks.fp32 = fp32;
+  return fp32 ? select_kernels_t<float>(n, n_pol, ks) : select_kernels_t<double>(n, n_pol, ks);
 }
 
 }  // namespace ssfm

@@ -82,7 +82,7 @@ def _good(**kw):
     dict(sample_rate_hz=math.inf), dict(span_km=-1.0), dict(alpha_db_per_km=math.nan),
     dict(beta2_ps2_per_km=math.inf), dict(gamma_per_w_km=math.nan),
     dict(nl_factor=math.inf), dict(edfa_gain_db=math.nan), dict(edfa_nf_db=math.nan),
-    dict(carrier_hz=-1.0), dict(flags=1), dict(reserved=3),
+    dict(carrier_hz=-1.0), dict(flags=2), dict(flags=3), dict(reserved=3),
 ])
 def test_invalid_links_are_rejected_without_a_device(bad):
     with pytest.raises(ssfm.SsfmError) as e:

@@ -39,3 +39,32 @@ def test_matches_library_fft():
     for n in (16, 64, 12):
         x = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
         assert np.allclose(oracle.dft_direct(x), np.fft.fft(x, axis=-1), atol=1e-12)
+
+
+def test_dft_bins_pins():
+    # every bin of a short transform equals the DFT-matrix sum
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((2, 64)) + 1j * rng.standard_normal((2, 64))
+    assert np.allclose(oracle.dft_bins(x, np.arange(64)), oracle.dft_direct(x), atol=1e-12)
+    # inverse of forward: n x (all bins, n = 64)
+    X = oracle.dft_bins(x, np.arange(64))
+    assert np.allclose(oracle.dft_bins(X, np.arange(64), inverse=True), 64 * x, atol=1e-11)
+    # closed forms at a long length, sampled bins: a delta at m gives the
+    # phase ramp exp(-2 pi i k m / n), a complex exponential at frequency f
+    # gives n at bin f and 0 elsewhere
+    n = 1 << 16
+    bins = np.array([0, 1, 7, 4097, 30000, n - 1])
+    e = np.zeros(n, complex)
+    e[12345] = 1.0
+    ramp = np.exp(-2j * np.pi * ((bins * 12345) % n) / n)
+    assert np.allclose(oracle.dft_bins(e, bins), ramp, atol=1e-12)
+    t = np.arange(n)
+    tone = np.exp(2j * np.pi * ((4097 * t) % n) / n)
+    want = np.where(bins == 4097, n, 0.0)
+    assert np.allclose(oracle.dft_bins(tone, bins), want, atol=1e-7)
+    # Parseval over all bins at a mid length
+    n = 4096
+    y = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    Y = oracle.dft_bins(y, np.arange(n), block=512)
+    assert abs(np.sum(np.abs(Y) ** 2) / (n * np.sum(np.abs(y) ** 2)) - 1) < 1e-12
+
