@@ -181,17 +181,25 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
  * complex64; the reverse sweep of those spans carries the cotangent alone
  * and takes x from the store (y = x e^{i phi}, phi = coef sum|x|^2).  The
  * result differs from the reconstructing sweep by rounding only.
- * Workspace: (n_spans + 2) * batch * n_pol * n_samples * 8 bytes, plus the
- * kept spans' states, allocated on first use (and grown) and owned by the
- * plan; if the device refuses the states' allocation, fewer spans are kept.
+ * LDS-resident path (n_samples <= 2^13): one launch, one workgroup per
+ * realisation: a forward pass keeps every span's input, then each span, from
+ * the last, is recomputed from its input (the forward's arithmetic), keeping
+ * the input x of each nonlinear step, and the cotangent is pulled back
+ * through it (amplifier, then per step the linear step's adjoint and the
+ * nonlinear pullback with x); the state budget does not apply.
+ * Workspace: four-step path (n_spans + 2) * batch * n_pol * n_samples * 8
+ * bytes plus the kept spans' states; LDS-resident path (n_spans +
+ * steps_per_span) * batch * n_pol * n_samples * 8 bytes; allocated on first
+ * use (and grown) and owned by the plan; if the device refuses the states'
+ * allocation, fewer spans are kept.
  * Calls on one plan are serialised, since they share that workspace: on the
  * host by a lock, and on the device by an event, so each call's work starts
  * after the previous call's work has finished, whatever stream each runs on
  * (concurrent calls on several streams give the results of consecutive
  * ones).  Growing the workspace waits for the previous call to finish.
  * Asynchronous like ssfm_forward.  Errors: SSFM_EINVAL (NULL/misaligned
- * pointers, batch < 1), SSFM_EUNSUPPORTED for n_samples < 2^14
- * (LDS-resident path), SSFM_ENOMEM, SSFM_EHIP. */
+ * pointers, batch < 1), SSFM_EUNSUPPORTED for an FP32-arithmetic plan,
+ * SSFM_ENOMEM, SSFM_EHIP. */
 int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
                  int64_t batch, uint64_t seed, void* stream);
 
@@ -204,17 +212,19 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
  * (128 MiB per device, held by every device that loads the library until the
  * process ends; its address is resolved per device by ssfm_plan).  The call
  * makes no hipMalloc/hipFree and creates no stream or event.
- *   Limit: (n_spans + 2) * batch * n_pol * n_samples * 8 bytes <= 128 MiB
- *   (e.g. batch <= 10 for 2^16 samples x 2 pol x 10 spans); larger calls
- *   return SSFM_EINVAL before any device work.
+ *   Limit: the workspace of ssfm_adjoint without kept states must fit in
+ *   128 MiB: (n_spans + 2) * batch * n_pol * n_samples * 8 bytes on the
+ *   four-step path (e.g. batch <= 10 for 2^16 samples x 2 pol x 10 spans),
+ *   (n_spans + steps_per_span) * batch * n_pol * n_samples * 8 bytes on the
+ *   LDS-resident path; larger calls return SSFM_EINVAL before any device
+ *   work.
  * Every call on a device shares that device's one scratch array, whatever
  * the plan: calls that overlap on one device (two streams, two threads, two
  * plans) race and give wrong results; the caller must order them.  Nothing
  * in the scratch needs to start at zero (each call writes what it reads).
  * Errors: those of ssfm_adjoint, SSFM_EINVAL also for the size limit and
- * while a profiling window is open on the plan, SSFM_EUNSUPPORTED for
- * n_samples < 2^14, SSFM_EHIP if the scratch address could not be
- * resolved. */
+ * while a profiling window is open on the plan, SSFM_EHIP if the scratch
+ * address could not be resolved. */
 int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad,
                          int64_t batch, uint64_t seed, void* stream);
 

@@ -728,13 +728,58 @@ int run_adjoint(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t bat
 }
 
 
+// The adjoint on the LDS-resident path: one launch (k1_adj) over the batch,
+// with the span inputs in ckpt ([batch][spans] fields) and one span's
+// nonlinear-step inputs per realisation in states ([batch][steps] fields).
+int run_adjoint_lds(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t batch,
+                    uint64_t seed, hipStream_t st, float2* ckpt, float2* states) {
+  ssfm::LdsArgs a{};
+  a.h_half = plan->h_half;
+  a.h_full = plan->h_full;
+  a.tw = plan->tw_n;
+  a.kappa = plan->d_kappa;
+  a.steps = plan->steps;
+  a.span_begin = 0;
+  a.span_end = plan->spans;
+  a.gspan = plan->gspan;
+  a.sigma_h = plan->sigma_h;
+  a.seed = seed;
+  a.realization0 = 0;
+  a.field_in = static_cast<const float2*>(field_in);
+  a.grad = static_cast<float2*>(grad);
+  a.ckpt = ckpt;
+  a.states = states;
+  // the forward pass, the recomputation and the reverse sweep of every span
+  const double bytes = 2.0 * (double)batch * plan->n_pol * (double)plan->n * sizeof(float2);
+  const hipError_t e =
+      launch(plan, KIND_LDS, bytes, st, [&] { return plan->ks.lds_adj(a, batch, st); });
+  if (e != hipSuccess) return api_fail_hip(e, "k1_adj launch");
+  return SSFM_OK;
+}
+
+// Workspace of an adjoint call, in elements: the four-step path's work
+// fields (state and cotangent) and span checkpoints; the LDS-resident path's
+// span inputs and one span's nonlinear-step inputs.
+void adjoint_workspace(const ssfm_plan_s* plan, int64_t batch, size_t* work, size_t* ckpt) {
+  const size_t slice = (size_t)batch * plan->n_pol * plan->n;
+  if (plan->ks.path == 1) {
+    *work = (size_t)plan->steps * slice;
+    *ckpt = (size_t)plan->spans * slice;
+  } else {
+    *work = 2 * slice;
+    *ckpt = (size_t)plan->spans * slice;
+  }
+}
+
 // ssfm_adjoint with the plan's adjoint lock held and the stream ordered after
 // the previous adjoint call.
 int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t batch,
                        uint64_t seed, hipStream_t st) {
   const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
-  const size_t ckpt_bytes = (size_t)plan->spans * slice * sizeof(float2);
-  const size_t work_bytes = 2 * slice * sizeof(float2);
+  size_t work_elems, ckpt_elems;
+  adjoint_workspace(plan, batch, &work_elems, &ckpt_elems);
+  const size_t ckpt_bytes = ckpt_elems * sizeof(float2);
+  const size_t work_bytes = work_elems * sizeof(float2);
   if (ckpt_bytes > plan->adj_ckpt_bytes || work_bytes > plan->adj_work_bytes) {
     // grow the workspace, once the previous call's work is done with it
     if (plan->adj_pending) {
@@ -754,6 +799,8 @@ int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int6
     plan->adj_ckpt_bytes = ckpt_bytes;
     plan->adj_work_bytes = work_bytes;
   }
+  if (plan->ks.path == 1)
+    return run_adjoint_lds(plan, field_in, grad, batch, seed, st, plan->adj_ckpt, plan->adj_work);
   // trailing spans whose nonlinear-step inputs the forward pass keeps, as
   // many as the plan's state budget holds (grown on demand; an allocation
   // the device refuses lowers the count)
@@ -1003,8 +1050,6 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad, int64_t bat
   if (rc != SSFM_OK) return rc;
   if (!grad) return api_fail(SSFM_EINVAL, "grad is NULL");
   if (((uintptr_t)grad & 7u) != 0) return api_fail(SSFM_EINVAL, "grad must be 8-byte aligned");
-  if (plan->ks.path != 2)
-    return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint needs n_samples >= 2^14 (four-step path)");
   if (plan->ks.fp32)
     return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint: no adjoint for the FP32-arithmetic variant");
   DeviceGuard guard(plan->device);
@@ -1036,28 +1081,30 @@ int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad, int
   if (rc != SSFM_OK) return rc;
   if (!grad) return api_fail(SSFM_EINVAL, "grad is NULL");
   if (((uintptr_t)grad & 7u) != 0) return api_fail(SSFM_EINVAL, "grad must be 8-byte aligned");
-  if (plan->ks.path != 2)
-    return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint_noalloc needs n_samples >= 2^14 (four-step path)");
   if (plan->ks.fp32)
     return api_fail(SSFM_EUNSUPPORTED, "ssfm_adjoint_noalloc: no adjoint for the FP32-arithmetic variant");
   if (plan->profiling)
     return api_fail(SSFM_EINVAL, "ssfm_adjoint_noalloc: a profiling window is open on the plan "
                                  "(its per-launch events would be created here)");
-  // work [2][batch] fields, then checkpoints [spans][batch]
-  const uint64_t slice = (uint64_t)batch * (uint64_t)plan->n_pol * (uint64_t)plan->n;
-  const uint64_t need = ((uint64_t)plan->spans + 2) * slice * sizeof(float2);
+  // four-step path: work [2][batch] fields, then checkpoints [spans][batch];
+  // LDS-resident path: [batch][steps] step inputs, then [batch][spans] span inputs
+  size_t work_elems, ckpt_elems;
+  adjoint_workspace(plan, batch, &work_elems, &ckpt_elems);
+  const uint64_t need = (uint64_t)(work_elems + ckpt_elems) * sizeof(float2);
   if (need > kNoallocScratchBytes)
     return api_fail(SSFM_EINVAL,
-                    "ssfm_adjoint_noalloc: (n_spans + 2) * batch * n_pol * n_samples * 8 = %llu "
-                    "bytes exceeds the %llu-byte device scratch; use ssfm_adjoint or a smaller batch",
+                    "ssfm_adjoint_noalloc: the workspace of %llu bytes exceeds the %llu-byte "
+                    "device scratch; use ssfm_adjoint or a smaller batch",
                     (unsigned long long)need, (unsigned long long)kNoallocScratchBytes);
   hipError_t why;
   float2* base = static_cast<float2*>(scratch_ptr(plan->device, &why));
   if (!base) return api_fail_hip(why, "ssfm_adjoint_noalloc: device scratch address");
   DeviceGuard guard(plan->device);
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
-  return run_adjoint(plan, field_in, grad, batch, seed, 0, static_cast<hipStream_t>(stream), base,
-                     base + 2 * slice, nullptr, 0);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->ks.path == 1)
+    return run_adjoint_lds(plan, field_in, grad, batch, seed, st, base + work_elems, base);
+  return run_adjoint(plan, field_in, grad, batch, seed, 0, st, base, base + work_elems, nullptr, 0);
 }
 
 

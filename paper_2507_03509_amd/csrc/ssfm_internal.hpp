@@ -84,6 +84,11 @@ struct LdsArgs {
   uint64_t seed;
   uint64_t realization0;
   const uint64_t* seeds;  // as ColArgs::seeds
+  // adjoint (k1_adj): spans 0..span_end-1 of realisations realization0 + b
+  const float2* field_in;  // forward input [batch][pol][n]
+  float2* grad;            // cotangent in and out [batch][pol][n]
+  float2* ckpt;            // span inputs [batch][spans][pol][n]
+  float2* states;          // nonlinear-step inputs of one span [batch][steps][pol][n]
 };
 
 // adjoint column pass over the cotangent alone, with the forward state read
@@ -115,6 +120,7 @@ struct KernelSet {
   bool fp32 = false;  // FP32-arithmetic variant (no adjoint kernels)
   int n1 = 0, n2 = 0;
   LdsLaunch lds = nullptr;
+  LdsLaunch lds_adj = nullptr;  // adjoint of the LDS-resident path (FP64)
   LdsDftLaunch lds_dft[2] = {nullptr, nullptr};  // the LDS-resident transform: forward, inverse
   RowLaunch row_wide = nullptr, row_narrow = nullptr;
   int rows_wide = 0, rows_narrow = 0;  // rows per workgroup

@@ -232,6 +232,91 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
 // ---------------------------------------------------------------------------
 
 
+// The adjoint's copy of k1_lds's span (the same operations in the same
+// order, so a span recomputed from its checkpoint repeats the forward's
+// states): for i = 0..steps, the nonlinear step i-1 (i > 0) then the linear
+// step with the half (i = 0, steps) or full operator; lane jj holds samples
+// jj + T r of every polarisation.  STORE: the input of nonlinear step i-1 is
+// also written, rounded to complex64, to states + (i-1) P N.
+template <int N, int P, bool STORE, typename L, typename CT>
+__device__ __forceinline__ void k1_span(CT (&reg)[P][16], L* lds1, const cd* __restrict__ h_half,
+                                        const cd* __restrict__ h_full,
+                                        const cd* __restrict__ tw,
+                                        const double* __restrict__ kappa, int steps, int jj,
+                                        float2* states) {
+  using R = decltype(CT{}.re);
+  constexpr int T = N / 16;
+  for (int i = 0; i <= steps; ++i) {
+    if (i > 0) {
+      if constexpr (STORE) {
+        float2* sp = states + (int64_t)(i - 1) * P * N;
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) store_c64(sp + q * N + jj + T * r, reg[q][r]);
+      }
+      // nonlinear phase of step i-1
+      const R kap = (R)kappa[i - 1];
+      R phi[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        R pw = 0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) pw = fma(reg[q][r].re, reg[q][r].re, fma(reg[q][r].im, reg[q][r].im, pw));
+        phi[r] = kap * pw;
+      }
+      for_each_phasor16(phi, [&](int r, CT rot) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) reg[q][r] = cmul(reg[q][r], rot);
+      });
+    }
+    const cd* h = (i == 0 || i == steps) ? h_half : h_full;
+    fft_multi<N, false, P, true, false>(reg, lds1, N + N / 16, 1, jj, tw);
+    // the dispersion multiply is FP64 in both arithmetic variants
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const cd hv = h[jj + T * r];
+#pragma unroll
+      for (int q = 0; q < P; ++q) reg[q][r] = cconv<CT>(cmul(cconv<cd>(reg[q][r]), hv));
+    }
+    fft_multi<N, true, P, true, false>(reg, lds1, N + N / 16, 1, jj, tw);
+  }
+}
+
+// The adjoint's copy of k1_lds's span end: loss factor, amplifier gain, ASE
+// (drawn into this lane's own LDS slots in a rolled loop, then added in an
+// unrolled one); the state is then the complex64 field.
+template <int N, int P, typename CT>
+__device__ __forceinline__ void k1_amplifier(CT (&reg)[P][16], unsigned char* lds1_raw,
+                                             double gspan, double sigma_h, int jj,
+                                             uint64_t key0, uint64_t key1) {
+  constexpr int T = N / 16;
+  float2* nbuf = reinterpret_cast<float2*>(lds1_raw);
+  const bool noisy = sigma_h != 0.0;
+  if (noisy) {
+    __syncthreads();  // the inverse FFT's LDS reads are done
+#pragma unroll 1
+    for (int r = 0; r < 16; ++r) {
+      const u64x4 w = philox4x64_10((uint64_t)(jj + T * r), 0, 0, 0, key0, key1);
+      nbuf[jj + T * r] = box_muller(w.w[0], w.w[1]);
+      if (P == 2) nbuf[N + jj + T * r] = box_muller(w.w[2], w.w[3]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      cd v = cscale(cconv<cd>(reg[q][r]), gspan);
+      if (noisy) {
+        const float2 g = nbuf[q * N + jj + T * r];
+        v.re = fma(sigma_h, (double)g.x, v.re);
+        v.im = fma(sigma_h, (double)g.y, v.im);
+      }
+      reg[q][r] = cconv<CT>(round_c64(v));
+    }
+  }
+}
+
 template <int N, int P, typename L, typename R>
 __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
   using CT = cplx<R>;
@@ -309,6 +394,115 @@ __global__ __launch_bounds__(N / 16) void k1_lds(LdsArgs a) {
   for (int q = 0; q < P; ++q)
 #pragma unroll
     for (int r = 0; r < 16; ++r) store_c64(fp + q * N + jj + T * r, reg[q][r]);
+}
+
+// Adjoint of the LDS-resident path (FP64), one realisation per workgroup, the
+// whole link in one launch, with span checkpoints and in-span recomputation:
+//   1. forward pass from field_in, writing the input of every span (complex64,
+//      exact: the state at a span boundary is the complex64 field) to ckpt;
+//   2. for each span from the last: recompute its split steps from its
+//      checkpoint with the forward's arithmetic (the same states, bit for
+//      bit), writing each nonlinear step's input x to this realisation's
+//      step slices; then pull the cotangent g = dL/dA* back through the
+//      span in reverse: amplifier g <- gspan g; per step i = steps..0 the
+//      linear step's adjoint (FFT, x conj(H), IFFT) and, for i > 0, the
+//      nonlinear step's pullback with its input x (y = x e^{i phi},
+//      phi = kappa sum_q |x_q|^2):
+//        g' = g e^{-i phi},  s = -Im sum_q conj(g'_q) x_q,  g <- g' + 2 s kappa x.
+//      All polarisations of a sample sit in one lane, so the sums are local.
+// The cotangent waits in the grad buffer (complex64) while a span is
+// recomputed; every lane reads back only the samples it wrote.
+template <int N, int P, typename L>
+__global__ __launch_bounds__(N / 16) void k1_adj(LdsArgs a) {
+  constexpr int T = N / 16;
+  extern __shared__ __align__(16) unsigned char lds1_raw[];
+  L* lds1 = reinterpret_cast<L*>(lds1_raw);
+  const int jj = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const int64_t slice = (int64_t)P * N;
+  const float2* xin = a.field_in + b * slice;
+  float2* gp = a.grad + b * slice;
+  float2* ck = a.ckpt + b * a.span_end * slice;        // [spans][P][N]
+  float2* st = a.states + b * (int64_t)a.steps * slice;  // [steps][P][N]
+  const uint64_t key0 = a.seed;
+  const uint64_t rkey = (a.realization0 + (uint64_t)b) * 65536ull;
+  cd reg[P][16];
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) reg[q][r] = load_c64(xin + q * N + jj + T * r);
+  for (int s = 0; s < a.span_end; ++s) {
+    float2* cs = ck + s * slice;
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) store_c64(cs + q * N + jj + T * r, reg[q][r]);
+    if (s + 1 == a.span_end) break;  // the last span's output is not needed
+    k1_span<N, P, false>(reg, lds1, a.h_half, a.h_full, a.tw, a.kappa, a.steps, jj, nullptr);
+    k1_amplifier<N, P>(reg, lds1_raw, a.gspan, a.sigma_h, jj, key0, rkey + (uint64_t)s);
+  }
+  for (int s = a.span_end - 1; s >= 0; --s) {
+    const float2* cs = ck + s * slice;
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) reg[q][r] = load_c64(cs + q * N + jj + T * r);
+    k1_span<N, P, true>(reg, lds1, a.h_half, a.h_full, a.tw, a.kappa, a.steps, jj, st);
+    // the cotangent, through the amplifier
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) reg[q][r] = cscale(load_c64(gp + q * N + jj + T * r), a.gspan);
+    for (int i = a.steps; i >= 0; --i) {
+      const cd* h = (i == 0 || i == a.steps) ? a.h_half : a.h_full;
+      fft_multi<N, false, P, true, false>(reg, lds1, N + N / 16, 1, jj, a.tw);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const cd hv = h[jj + T * r];
+#pragma unroll
+        for (int q = 0; q < P; ++q) reg[q][r] = cmulc(reg[q][r], hv);
+      }
+      fft_multi<N, true, P, true, false>(reg, lds1, N + N / 16, 1, jj, a.tw);
+      if (i > 0) {
+        const float2* sp = st + (int64_t)(i - 1) * slice;
+        const double kap = a.kappa[i - 1];
+        double phi[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          double pw = 0.0;
+#pragma unroll
+          for (int q = 0; q < P; ++q) {
+            const cd x = load_c64(sp + q * N + jj + T * r);
+            pw = fma(x.re, x.re, fma(x.im, x.im, pw));
+          }
+          phi[r] = -kap * pw;
+        }
+        // x is read again below rather than held in registers across the
+        // phasors (a compiler barrier, no instruction)
+        asm volatile("" ::: "memory");
+        for_each_phasor16(phi, [&](int r, cd e) {  // e = e^{-i phi}
+          cd x[P];
+          double sgn = 0.0;
+#pragma unroll
+          for (int q = 0; q < P; ++q) {
+            x[q] = load_c64(sp + q * N + jj + T * r);
+            reg[q][r] = cmul(reg[q][r], e);  // g'
+            sgn = fma(reg[q][r].im, x[q].re, fma(-reg[q][r].re, x[q].im, sgn));
+          }
+          const double w = 2.0 * sgn * kap;  // s = -Im sum conj(g') x = sum (g'.im x.re - g'.re x.im)
+#pragma unroll
+          for (int q = 0; q < P; ++q) {
+            reg[q][r].re = fma(w, x[q].re, reg[q][r].re);
+            reg[q][r].im = fma(w, x[q].im, reg[q][r].im);
+          }
+        });
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) store_c64(gp + q * N + jj + T * r, reg[q][r]);
+  }
 }
 
 // The LDS-resident transform alone (ssfm_dft): k1_lds's load, one FFT (or
@@ -409,6 +603,14 @@ static hipError_t launch_k1_dft(float2* field, const cd* tw, int64_t batch, hipS
   return hipGetLastError();
 }
 
+template <int N, int P, typename L>
+static hipError_t launch_k1_adj(const LdsArgs& a, int64_t batch, hipStream_t st) {
+  constexpr int T = N / 16;
+  const size_t lds = k1_lds_bytes<N, P, L>();
+  hipLaunchKernelGGL((k1_adj<N, P, L>), dim3((unsigned)batch), dim3(T), lds, st, a);
+  return hipGetLastError();
+}
+
 template <int N, int P, typename L, typename R>
 static hipError_t prepare_k1() {
   const size_t lds = k1_lds_bytes<N, P, L>();
@@ -419,6 +621,9 @@ static hipError_t prepare_k1() {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  if constexpr (sizeof(R) == 8)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k1_adj<N, P, L>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   return hipSuccess;
 }
 
@@ -490,6 +695,7 @@ static void fill_lds(KernelSet& ks, int n_pol) {
   constexpr bool F64 = sizeof(R) == 8;
   using L1 = std::conditional_t<F64, cd, float2>;
   using L2 = std::conditional_t<F64 && N <= 4096, cd, float2>;
+  if constexpr (F64) ks.lds_adj = n_pol == 1 ? &launch_k1_adj<N, 1, L1> : &launch_k1_adj<N, 2, L2>;
   if (n_pol == 1) {
     ks.lds = &launch_k1<N, 1, L1, R>;
     ks.lds_dft[0] = &launch_k1_dft<N, 1, L1, R, false>;
