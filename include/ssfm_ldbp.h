@@ -72,6 +72,29 @@ int ssfm_ldbp_create(const ssfm_ldbp_desc* desc, int hip_device, ssfm_ldbp_t* ou
  * still be running. */
 int ssfm_ldbp_destroy(ssfm_ldbp_t h);
 
+/* Initial parameters that back-propagate `link` (host function, no device
+ * work): K = n_spans * steps_per_span steps, the last span first.  Step k
+ * covers 1/S of a span (S = steps_per_span): its filter is the T-tap
+ * truncation, centred (offsets t - (T-1)/2), of the impulse response of the
+ * inverse dispersion exp(-i (beta2/2) w^2 L/S) on the link's n_samples-point
+ * DFT grid (inverse DFT by its direct sum), divided by the truncated filter's
+ * peak gain over that grid (so that no frequency is amplified step after
+ * step) and, for the first step of each span (k mod S = 0), by the span's
+ * field gain sqrt(G) exp(-alpha L/2) (undoing the amplifier); its Kerr
+ * coefficient is xi_k = -c_nl gamma h_nl exp(-alpha z), the forward model's
+ * nonlinear phase per unit power over the step, with h_nl =
+ * 2 sinh(alpha L/(2S))/alpha and z = L - (k mod S + 1/2) L/S the step's
+ * midpoint (the model of Haeger and Pfister, initialised from the link).
+ *   taps: host complex128 [K][T] (double re, im), written
+ *   xi:   host double [K], written
+ * The link's n_samples may be up to 2^22 (the LDBP range); its span count,
+ * fibre and amplifier parameters are used, the rest ignored.  Errors:
+ * SSFM_EINVAL for NULL pointers, T not odd in 1..15, S not in 1..4,
+ * K > 4096, n_samples not a power of two in [2^6, 2^22], non-finite
+ * parameters. */
+int ssfm_ldbp_init_params(const ssfm_link* link, int32_t n_taps, int32_t steps_per_span,
+                          double* taps, double* xi);
+
 /* Bytes of the checkpoint buffer for `batch` realisations:
  * (K/S - 1) * batch * P * N * 8 (0 when K = S). */
 int ssfm_ldbp_checkpoint_bytes(ssfm_ldbp_t h, int64_t batch, int64_t* bytes);

@@ -4,7 +4,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
+#include <vector>
 
 #include "host_common.hpp"
 #include "ldbp_internal.hpp"
@@ -212,6 +214,86 @@ int run_forward(ssfm_ldbp_s* h, const float2* src, float2* dst, const double* xi
 }  // namespace
 
 extern "C" {
+
+int ssfm_ldbp_init_params(const ssfm_link* link, int32_t n_taps, int32_t steps_per_span,
+                          double* taps, double* xi) {
+  ssfm::api_clear_error();
+  if (!link || !taps || !xi) return api_fail(SSFM_EINVAL, "link, taps and xi must be non-NULL");
+  const int64_t n = link->n_samples;
+  if (link->n_pol != 1 && link->n_pol != 2) return api_fail(SSFM_EINVAL, "n_pol must be 1 or 2");
+  if (n < 64 || n > (int64_t(1) << 22) || (n & (n - 1)) != 0)
+    return api_fail(SSFM_EINVAL, "n_samples must be a power of two in [2^6, 2^22]");
+  if (n_taps < 1 || n_taps > 15 || n_taps % 2 == 0)
+    return api_fail(SSFM_EINVAL, "n_taps must be odd, 1..15 (got %d)", n_taps);
+  if (steps_per_span < 1 || steps_per_span > 4)
+    return api_fail(SSFM_EINVAL, "steps_per_span must be 1..4 (got %d)", steps_per_span);
+  if (link->n_spans < 1 || (int64_t)link->n_spans * steps_per_span > 4096)
+    return api_fail(SSFM_EINVAL, "n_spans * steps_per_span must be 1..4096");
+  const double vals[] = {link->sample_rate_hz, link->span_km, link->alpha_db_per_km,
+                         link->beta2_ps2_per_km, link->gamma_per_w_km, link->edfa_gain_db};
+  for (double v : vals)
+    if (!std::isfinite(v)) return api_fail(SSFM_EINVAL, "link parameters must be finite");
+  if (link->sample_rate_hz <= 0 || link->span_km <= 0)
+    return api_fail(SSFM_EINVAL, "sample_rate_hz and span_km must be > 0");
+  const double kPi = 3.14159265358979323846;
+  const double fs = link->sample_rate_hz;
+  const double span = link->span_km * 1e3;
+  const double alpha = link->alpha_db_per_km * std::log(10.0) / 10.0 / 1e3;
+  const double beta2 = link->beta2_ps2_per_km * 1e-27;
+  const double gamma = link->gamma_per_w_km * 1e-3;
+  const double cnl = std::isnan(link->nl_factor) ? (link->n_pol == 1 ? 1.0 : 8.0 / 9.0)
+                                                 : link->nl_factor;
+  const double gain = std::pow(10.0, link->edfa_gain_db / 10.0);
+  const int S = steps_per_span, T = n_taps, c = (T - 1) / 2;
+  const double step = span / S;
+  // response of the inverse dispersion over one step, exp(-i (beta2/2) w^2 step),
+  // w the angular frequency of DFT bin k (bins above n/2 are negative)
+  std::vector<double> ph((size_t)n);
+  for (int64_t k = 0; k < n; ++k) {
+    const double w = 2.0 * kPi * (double)(k < n / 2 ? k : k - n) * fs / (double)n;
+    ph[(size_t)k] = -0.5 * beta2 * w * w * step;
+  }
+  // the impulse response at the T centred offsets m = t - c (mod n): the
+  // inverse DFT by its direct sum, exponents k m reduced mod n
+  std::vector<double> hre((size_t)T), him((size_t)T);
+  std::vector<int64_t> m((size_t)T);
+  for (int t = 0; t < T; ++t) {
+    m[(size_t)t] = ((int64_t)(t - c) % n + n) % n;
+    double sr = 0.0, si = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+      const double a = ph[(size_t)k] + 2.0 * kPi * (double)((k * m[(size_t)t]) % n) / (double)n;
+      sr += std::cos(a);
+      si += std::sin(a);
+    }
+    hre[(size_t)t] = sr / (double)n;
+    him[(size_t)t] = si / (double)n;
+  }
+  // peak gain of the truncated filter on the n-point grid
+  double peak = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    double sr = 0.0, si = 0.0;
+    for (int t = 0; t < T; ++t) {
+      const double a = -2.0 * kPi * (double)((k * m[(size_t)t]) % n) / (double)n;
+      const double ca = std::cos(a), sa = std::sin(a);
+      sr += hre[(size_t)t] * ca - him[(size_t)t] * sa;
+      si += hre[(size_t)t] * sa + him[(size_t)t] * ca;
+    }
+    peak = std::max(peak, std::sqrt(sr * sr + si * si));
+  }
+  const double gspan = std::sqrt(gain) * std::exp(-0.5 * alpha * span);
+  const double hnl = alpha == 0.0 ? step : 2.0 * std::sinh(0.5 * alpha * step) / alpha;
+  const int64_t K = (int64_t)link->n_spans * S;
+  for (int64_t k = 0; k < K; ++k) {
+    const int j = (int)(k % S);  // sub-step within its span, from the span's end
+    const double scale = peak * (j == 0 ? gspan : 1.0);
+    for (int t = 0; t < T; ++t) {
+      taps[2 * (k * T + t)] = hre[(size_t)t] / scale;
+      taps[2 * (k * T + t) + 1] = him[(size_t)t] / scale;
+    }
+    xi[k] = -cnl * gamma * hnl * std::exp(-alpha * (span - (j + 0.5) * step));
+  }
+  return SSFM_OK;
+}
 
 int ssfm_ldbp_create(const ssfm_ldbp_desc* desc, int hip_device, ssfm_ldbp_t* out) {
   ssfm::api_clear_error();

@@ -54,8 +54,12 @@ def _lib() -> ctypes.CDLL:
         lib.ssfm_ldbp_forward.argtypes = [VP, VP, VP, VP, VP, I64, VP, VP]
         lib.ssfm_ldbp_loss.argtypes = [VP, VP, VP, VP, I64, VP, VP, VP]
         lib.ssfm_ldbp_backward.argtypes = [VP, VP, VP, VP, VP, I64, VP, VP, VP, VP, VP]
+        from . import SsfmLink
+        lib.ssfm_ldbp_init_params.argtypes = [ctypes.POINTER(SsfmLink), ctypes.c_int32,
+                                              ctypes.c_int32, VP, VP]
         for name in ("ssfm_ldbp_create", "ssfm_ldbp_destroy", "ssfm_ldbp_checkpoint_bytes",
-                     "ssfm_ldbp_forward", "ssfm_ldbp_loss", "ssfm_ldbp_backward"):
+                     "ssfm_ldbp_forward", "ssfm_ldbp_loss", "ssfm_ldbp_backward",
+                     "ssfm_ldbp_init_params"):
             getattr(lib, name).restype = ctypes.c_int
         _ready = True
     return lib
@@ -223,46 +227,17 @@ class Ldbp:
 def init_params(link, n_taps: int, steps_per_span: int):
     """Taps (complex128 [K, T]) and Kerr coefficients (float64 [K]) that
     back-propagate ``link`` (any object with the fields of ``ssfm_link``),
-    K = n_spans * steps_per_span, last span first.
-
-    Step k covers 1/S of a span (S = steps_per_span): its filter is the
-    T-tap truncation, centred, of the impulse response of the inverse
-    dispersion exp(-i (beta2/2) w^2 L/S) on the link's n-point grid, divided
-    by the truncated filter's peak gain (so that no frequency is amplified
-    step after step), and, for the first step of each span, by the span's
-    field gain sqrt(G) exp(-alpha L/2) (undoing the amplifier).  Its
-    coefficient is -c_nl gamma h_nl exp(-alpha z), the forward model's
-    nonlinear phase per unit power over the step, with
-    h_nl = 2 sinh(alpha L/(2S))/alpha and z the step's midpoint in the span.
-    Host-side model initialisation (NumPy), not part of the GPU path."""
+    K = n_spans * steps_per_span, last span first: ssfm_ldbp_init_params."""
     import numpy as np
-    n = int(link.n_samples)
-    fs = float(link.sample_rate_hz)
-    span = float(link.span_km) * 1e3
-    alpha = float(link.alpha_db_per_km) * np.log(10.0) / 10.0 / 1e3
-    beta2 = float(link.beta2_ps2_per_km) * 1e-27
-    gamma = float(link.gamma_per_w_km) * 1e-3
-    cnl = getattr(link, "nl_factor", None)
-    if cnl is None or cnl != cnl:
-        cnl = 1.0 if int(link.n_pol) == 1 else 8.0 / 9.0
-    gain = 10.0 ** (float(getattr(link, "edfa_gain_db", 0.0)) / 10.0)
-    s_steps = int(steps_per_span)
-    step = span / s_steps
-    w = 2.0 * np.pi * np.fft.fftfreq(n, d=1.0 / fs)
-    impulse = np.fft.ifft(np.exp(-0.5j * beta2 * w * w * step))
-    half = (int(n_taps) - 1) // 2
-    offsets = np.arange(int(n_taps)) - half
-    h = impulse[offsets % n]
-    circ = np.zeros(n, dtype=np.complex128)
-    np.add.at(circ, offsets % n, h)
-    h = h / np.abs(np.fft.fft(circ)).max()
-    g_span = np.sqrt(gain) * np.exp(-0.5 * alpha * span)
-    h_nl = step if alpha == 0.0 else 2.0 * np.sinh(0.5 * alpha * step) / alpha
-    k_total = int(link.n_spans) * s_steps
-    taps = np.tile(h, (k_total, 1))
-    taps[::s_steps] /= g_span
-    j = np.arange(k_total) % s_steps
-    xi = -cnl * gamma * h_nl * np.exp(-alpha * (span - (j + 0.5) * step))
+    from . import make_link
+    k = int(link.n_spans) * int(steps_per_span)
+    taps = np.empty((k, int(n_taps)), dtype=np.complex128)
+    xi = np.empty(k, dtype=np.float64)
+    s = make_link(link)
+    _check(_lib().ssfm_ldbp_init_params(
+        ctypes.byref(s), int(n_taps), int(steps_per_span),
+        taps.ctypes.data_as(ctypes.c_void_p), xi.ctypes.data_as(ctypes.c_void_p)),
+        "ssfm_ldbp_init_params")
     return taps, xi
 
 

@@ -179,3 +179,23 @@ def test_ldbp_init_params_match_the_oracle():
         tb, xb = oracle.init_params(ln, t, s)
         np.testing.assert_allclose(ta, tb, rtol=1e-12, atol=1e-15)
         np.testing.assert_allclose(xa, xb, rtol=1e-12, atol=0)
+
+
+def test_ldbp_init_params_rejects_invalid_arguments():
+    # host function: no device involved
+    import ctypes
+    import numpy as np
+    from paper_2507_03509_amd import ldbp
+    from workloads import LDBP
+    ln = LDBP.workload.link
+    lib = ssfm.load_library()
+    ldbp._lib()
+    s = ssfm.make_link(ln)
+    taps = np.empty((40, 15), np.complex128)
+    xi = np.empty(40)
+    tp, xp = taps.ctypes.data_as(ctypes.c_void_p), xi.ctypes.data_as(ctypes.c_void_p)
+    assert lib.ssfm_ldbp_init_params(ctypes.byref(s), 15, 2, tp, xp) == ssfm.SSFM_OK
+    for t, st in ((14, 2), (17, 2), (0, 2), (15, 0), (15, 5)):
+        assert lib.ssfm_ldbp_init_params(ctypes.byref(s), t, st, tp, xp) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_ldbp_init_params(ctypes.byref(s), 15, 2, None, xp) == ssfm.SSFM_EINVAL
+    assert lib.ssfm_ldbp_init_params(None, 15, 2, tp, xp) == ssfm.SSFM_EINVAL
