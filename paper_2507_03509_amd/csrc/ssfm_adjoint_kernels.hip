@@ -12,134 +12,138 @@ namespace ssfm {
 
 __device__ __forceinline__ double norm2(cd v) { return fma(v.re, v.re, v.im * v.im); }
 
+// Sum over the polarisations of a sample: across the lane pair (l, l ^ 32)
+// for two, the value itself for one.
+template <int P>
+__device__ __forceinline__ double pol_sum(double x) {
+  if constexpr (P == 2) return pair32_sum(x);
+  else return x;
+}
+
 // ---------------------------------------------------------------------------
 // K3 adjoint: column tiles of the work buffer holding, for realisation b, the
 // reconstructed forward state (at b) and the cotangent dL/dA* (at batch + b).
-// Lanes: field f (0 state, 1 cotangent) x polarisation x C columns x T.
+// The tile and lane map are the forward column pass's (C columns x N1 rows x
+// P polarisations; 8 columns, so every load and store moves 64-byte runs of
+// a row); a workgroup carries the state's tile first, then the cotangent's.
 //   AMODE_FIRST  state <- span-end checkpoint; both fields time -> mixed
 //   AMODE_NL     both mixed -> time; with y the state (output of the forward
-//                nonlinear step) and phi = kappa sum_q |y_q|^2:
-//                  state     x   = y e^{-i phi}            (inverse step)
-//                  cotangent g_x = g_y e^{-i phi} + 2 s kappa x,
-//                            s   = -Im sum_q conj(g_y,q) y_q (pullback)
-//                then both time -> mixed
+//                nonlinear step), e = e^{-i phi}, phi = kappa sum_q |y_q|^2:
+//                  state     x   = y e                       (inverse step)
+//                  cotangent g_x = ge + 2 s kappa x,  ge = g_y e,
+//                            s   = -Im sum_q conj(g_y,q) y_q = -Im sum_q conj(ge_q) x_q
+//                (y = x conj(e)); then both time -> mixed
 //   AMODE_LAST   cotangent mixed -> time, times the span gain (the pullback of
 //                the amplifier, applied at the end of the span's reverse sweep
-//                because everything in between is linear in the cotangent)
+//                because everything in between is linear in the cotangent);
+//                the state is not needed past the span start
+// Between the halves of AMODE_NL the lane keeps its x, rounded to complex64,
+// in LDS slots of its own (registers would spill), and the cotangent half
+// forms phi again from x (|x| = |y|).  The transforms exchange through LDS in
+// FP32 (the arithmetic stays FP64): with x's 32 KB that keeps a workgroup at
+// 64 KB, two per CU.  Each rounding is of the size of the complex64 field
+// store between kernels.  Sums over the polarisations are formed across the
+// lane pair, lower lane first.
 // ---------------------------------------------------------------------------
 template <int N1, int C, int P, int AMODE>
-__global__ __launch_bounds__(2 * P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k3_adj(AdjArgs a) {
   constexpr int T = N1 / 16;
+  static_assert(P == 1 || C * T >= 32, "two polarisations need lane pairs");
+  // [P][N1][C] transform exchange, then [16][lanes] the lanes' x
   extern __shared__ __align__(16) unsigned char lds_adj[];
-  cd* lds = reinterpret_cast<cd*>(lds_adj);
+  float2* lds = reinterpret_cast<float2*>(lds_adj);
+  float2* xl = lds + P * N1 * C;
   const int tid = threadIdx.x;
-  const int f = tid / (P * C * T);
-  const int rem0 = tid % (P * C * T);
-  const int p = rem0 / (C * T);
-  const int rem = rem0 % (C * T);
-  const int c = rem % C;
-  const int j = rem / C;
+  int p, c, j;
+  if constexpr (P == 2) {
+    const int l = tid & 63;
+    const int q = (tid >> 6) * 32 + (l & 31);
+    p = l >> 5;
+    c = q % C;
+    j = q / C;
+  } else {
+    p = 0;
+    c = tid % C;
+    j = tid / C;
+  }
   const int tiles = a.n2 / C;
   const unsigned G = gridDim.x;
   const unsigned id = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
   const int64_t b = id / tiles;
   const int col0 = (int)(id % tiles) * C;
-  // FFT regions: one per (field, polarisation), N1 + N1/16 padded rows of C
-  constexpr int RS = (N1 + N1 / 16) * C;
-  cd* mylds = lds + (f * P + p) * RS + c;
-  // Field f of a wave is one value when a field's lanes fill whole waves:
-  // then the tile is addressed through buffer resources (wave-uniform base,
-  // one lane offset), else through per-element 64-bit addresses.
-  constexpr bool WAVE_F = (P * C * T) % 64 == 0;
-  const float2* rbase = a.work + (f * a.batch + b) * P * a.n + col0;  // realisation, column col0
-  const float2* sbase = rbase;
-  if constexpr (AMODE == AMODE_FIRST) {
-    if (f == 0) sbase = a.ckpt + b * P * a.n + col0;
-  }
   const uint32_t tile_bytes = (uint32_t)((P * a.n - col0) * 8);
   const uint32_t lane_off = (uint32_t)(p * a.n + c + (int64_t)j * a.n2) * 8u;
   const uint32_t step = (uint32_t)(T * a.n2) * 8u;
-  col_buf fb{}, sb{};
-  if constexpr (WAVE_F) {
-    fb = make_col_buf(wave_uniform(rbase), tile_bytes, lane_off, step);
-    sb = make_col_buf(wave_uniform(sbase), tile_bytes, lane_off, step);
-  }
-  float2* fp = const_cast<float2*>(rbase) + p * a.n + c;
-  const float2* src = sbase + p * a.n + c;
-  cd reg[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    if constexpr (WAVE_F) reg[r] = col_load(sb, r);
-    else reg[r] = load_c64(src + (int64_t)(j + T * r) * a.n2);
-  }
+  const col_buf sb = make_col_buf(a.work + b * P * a.n + col0, tile_bytes, lane_off, step);
+  const col_buf gb =
+      make_col_buf(a.work + (a.batch + b) * P * a.n + col0, tile_bytes, lane_off, step);
+  float2* mylds = lds + p * (N1 * C) + c;
   const lane_twiddles<N1> ltw(a.tw1, j);
-
+  cd reg[16];
   if constexpr (AMODE == AMODE_FIRST) {
-    fft<N1, false, 2, false>(reg, mylds, C, j, ltw);
+    // state <- span-end checkpoint; both fields time -> mixed
+    const col_buf kb = make_col_buf(a.ckpt + b * P * a.n + col0, tile_bytes, lane_off, step);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) reg[r] = col_load<cd>(kb, r);
+    fft<N1, false, 0, false>(reg, mylds, C, j, ltw);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) col_store(sb, r, reg[r]);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) reg[r] = col_load<cd>(gb, r);
+    fft<N1, false, 0, false>(reg, mylds, C, j, ltw);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) col_store(gb, r, reg[r]);
   } else if constexpr (AMODE == AMODE_NL) {
-    fft<N1, true, 2, false>(reg, mylds, C, j, ltw);
-    // exchange in natural (row, column) order: every lane publishes its
-    // value and reads only those it does not hold (state lanes: the other
-    // polarisation's state; cotangent lanes: both states and the other
-    // polarisation's cotangent)
-    __syncthreads();  // the inverse FFT's LDS reads are done
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lds[((f * P + p) * N1 + j + T * r) * C + c] = reg[r];
-    __syncthreads();
-    constexpr int F = N1 * C;  // one field-polarisation plane
-    double phi[16];
-    if (f == 0) {
-      // x = y e^{-i phi}; the power is one add of per-polarisation terms
-      // (commutative, so every lane of the sample gets the same phase)
+    for (int r = 0; r < 16; ++r) reg[r] = col_load<cd>(sb, r);
+    fft<N1, true, 0, false>(reg, mylds, C, j, ltw);
+    {
+      double phi[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = (j + T * r) * C + c;
-        double pw = norm2(reg[r]);
-        if constexpr (P == 2) pw = pw + norm2(lds[(1 - p) * F + i]);
-        phi[r] = -a.kappa * pw;
-      }
+      for (int r = 0; r < 16; ++r) phi[r] = -a.kappa * pol_sum<P>(norm2(reg[r]));
       for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
-    } else {
-      // g_x = g_y e^{-i phi} + 2 s kappa x,  s = -Im sum_q conj(g_q) y_q
-      // (the states and the other cotangent are read from LDS again in the
-      // second loop rather than held in registers)
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      xl[r * (P * C * T) + tid] = make_float2((float)reg[r].re, (float)reg[r].im);
+    fft<N1, false, 0, false>(reg, mylds, C, j, ltw);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) col_store(sb, r, reg[r]);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) reg[r] = col_load<cd>(gb, r);
+    fft<N1, true, 0, false>(reg, mylds, C, j, ltw);
+    {
+      double phi[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int i = (j + T * r) * C + c;
-        double pw = norm2(lds[p * F + i]);
-        if constexpr (P == 2) pw = pw + norm2(lds[(1 - p) * F + i]);
-        phi[r] = -a.kappa * pw;
+        const float2 v = xl[r * (P * C * T) + tid];
+        phi[r] = -a.kappa * pol_sum<P>(norm2(cd{(double)v.x, (double)v.y}));
       }
-      for_each_phasor16(phi, [&](int r, cd e) {  // e = e^{-i phi}
-        const int i = (j + T * r) * C + c;
-        const cd yp = lds[p * F + i];
-        double s = fma(reg[r].im, yp.re, -reg[r].re * yp.im);
-        if constexpr (P == 2) {
-          const cd yo = lds[(1 - p) * F + i];
-          const cd go = lds[(P + 1 - p) * F + i];
-          s = fma(go.im, yo.re, fma(-go.re, yo.im, s));
-        }
+      // x is read again below rather than held across the phasor (the
+      // fence keeps the compiler from merging the two reads, which would
+      // spill)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      for_each_phasor16(phi, [&](int r, cd e) {
+        const float2 v = xl[r * (P * C * T) + tid];
+        const cd x{(double)v.x, (double)v.y};
+        const cd ge = cmul(reg[r], e);
+        const double s = pol_sum<P>(fma(ge.im, x.re, -ge.re * x.im));
         const double w = 2.0 * s * a.kappa;
-        const cd x = cmul(yp, e);
-        const cd gx = cmul(reg[r], e);
-        reg[r] = {fma(w, x.re, gx.re), fma(w, x.im, gx.im)};
+        reg[r] = {fma(w, x.re, ge.re), fma(w, x.im, ge.im)};
       });
     }
-    fft<N1, false, 2, false>(reg, mylds, C, j, ltw);
-  }
-  if constexpr (AMODE == AMODE_LAST) {
-    // every lane transforms (the block barriers need all of them); only the
-    // cotangent is stored, the state is not needed past the span start
-    fft<N1, true, 2, false>(reg, mylds, C, j, ltw);
-    if (f == 0) return;
+    fft<N1, false, 0, false>(reg, mylds, C, j, ltw);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) reg[r] = round_c64(cscale(reg[r], a.gspan));
-  }
+    for (int r = 0; r < 16; ++r) col_store(gb, r, reg[r]);
+  } else {
+    // the cotangent mixed -> time, times the span gain; the state is not
+    // needed past the span start
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    if constexpr (WAVE_F) col_store(fb, r, reg[r]);
-    else store_c64(fp + (int64_t)(j + T * r) * a.n2, reg[r]);
+    for (int r = 0; r < 16; ++r) reg[r] = col_load<cd>(gb, r);
+    fft<N1, true, 0, false>(reg, mylds, C, j, ltw);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) col_store(gb, r, round_c64(cscale(reg[r], a.gspan)));
   }
 }
 
@@ -233,29 +237,6 @@ void k3_adj_stored(AdjStoredArgs a) {
 // padded FFT regions of both fields; the nonlinear exchange (2 P N1 C values)
 // fits in them
 template <int N1, int C, int P>
-constexpr size_t adj_lds_bytes() {
-  return (size_t)2 * P * (N1 + N1 / 16) * C * sizeof(cd);
-}
-
-template <int N1, int C, int P, int AMODE>
-static hipError_t launch_k3_adj(const AdjArgs& a, hipStream_t st) {
-  constexpr int T = N1 / 16;
-  const size_t lds = adj_lds_bytes<N1, C, P>();
-  const unsigned blocks = (unsigned)(a.batch * (a.n2 / C));
-  hipLaunchKernelGGL((k3_adj<N1, C, P, AMODE>), dim3(blocks), dim3(2 * P * C * T), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int N1, int C, int P, int AMODE>
-static hipError_t prepare_k3_adj() {
-  const size_t lds = adj_lds_bytes<N1, C, P>();
-  if (lds > 65536)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_adj<N1, C, P, AMODE>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return hipSuccess;
-}
-
-template <int N1, int C, int P>
 static hipError_t launch_k3_adj_stored(const AdjStoredArgs& a, int64_t batch, hipStream_t st) {
   constexpr int T = N1 / 16;
   const size_t lds = (size_t)P * C * N1 * sizeof(cd);
@@ -273,11 +254,34 @@ static hipError_t prepare_k3_adj_stored() {
   return hipSuccess;
 }
 
-// adjoint column tiles: 4 columns (2 at N1 = 512), both fields, FP64 LDS
-// (68 KB per workgroup with the padding)
+template <int N1, int C, int P>
+constexpr size_t adj_lds_bytes() {
+  return (size_t)2 * P * N1 * C * sizeof(float2);  // exchange + the lanes' x
+}
+
+template <int N1, int C, int P, int AMODE>
+static hipError_t launch_k3_adj(const AdjArgs& a, hipStream_t st) {
+  constexpr int T = N1 / 16;
+  const size_t lds = adj_lds_bytes<N1, C, P>();
+  const unsigned blocks = (unsigned)(a.batch * (a.n2 / C));
+  hipLaunchKernelGGL((k3_adj<N1, C, P, AMODE>), dim3(blocks), dim3(P * C * T), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int N1, int C, int P, int AMODE>
+static hipError_t prepare_k3_adj() {
+  const size_t lds = adj_lds_bytes<N1, C, P>();
+  if (lds > 65536)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k3_adj<N1, C, P, AMODE>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
+// adjoint column tiles: the forward pass's wide tile (8 columns, 4 at
+// N1 = 512; 64 KB of LDS), state then cotangent
 template <int N1, int P>
 static void fill_adj(KernelSet& ks) {
-  constexpr int C = N1 == 512 ? 2 : 4;
+  constexpr int C = N1 == 512 ? 4 : 8;
   ks.adj[AMODE_FIRST] = &launch_k3_adj<N1, C, P, AMODE_FIRST>;
   ks.adj[AMODE_NL] = &launch_k3_adj<N1, C, P, AMODE_NL>;
   ks.adj[AMODE_LAST] = &launch_k3_adj<N1, C, P, AMODE_LAST>;

@@ -358,8 +358,10 @@ int64_t launches_per_call(const ssfm_plan_s* p) {
 
 // Launch shape of a four-step call: SSFM_COLUMNS override (the width of the
 // wide or the narrow column tile, with the matching row workgroup), else the shape
-// ssfm_plan_autotune recorded for this batch, else wide tiles once the batch
-// gives at least 512 column workgroups.
+// ssfm_plan_autotune recorded for this batch, else wide column tiles once the
+// batch gives at least 512 column workgroups, and 256-lane row workgroups
+// below 2^16 rows (64-lane ones from there on: measured faster on the 2^16 and
+// 2^18 links at large batches, where the grid holds several waves per SIMD).
 struct Shape4 {
   const ssfm::FourStepKernels* cols;
   ssfm::RowLaunch row;
@@ -386,7 +388,8 @@ Shape4 pick_shape(ssfm_plan_s* p, int64_t batch) {
     }
   }
   const bool w = batch * (p->ks.n2 / p->ks.wide.columns) >= 512;
-  return {w ? &p->ks.wide : &p->ks.narrow, w ? p->ks.row_wide : p->ks.row_narrow, w, w};
+  const bool wr = w && batch * p->n_pol * p->ks.n1 < 65536;
+  return {w ? &p->ks.wide : &p->ks.narrow, wr ? p->ks.row_wide : p->ks.row_narrow, w, wr};
 }
 
 // Graph replay for the four-step path (many launches per call); not while a
