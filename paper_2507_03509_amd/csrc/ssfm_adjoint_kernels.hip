@@ -37,23 +37,23 @@ __device__ __forceinline__ double pol_sum(double x) {
 //                the amplifier, applied at the end of the span's reverse sweep
 //                because everything in between is linear in the cotangent);
 //                the state is not needed past the span start
-// Between the halves of AMODE_NL the lane keeps its x, rounded to complex64,
-// in LDS slots of its own (registers would spill), and the cotangent half
-// forms phi again from x (|x| = |y|).  The transforms exchange through LDS in
-// FP32 (the arithmetic stays FP64): with x's 32 KB that keeps a workgroup at
-// 64 KB, two per CU.  Each rounding is of the size of the complex64 field
-// store between kernels.  Sums over the polarisations are formed across the
-// lane pair, lower lane first.
+// Between the halves of AMODE_NL the lane keeps its x (rounded to complex64)
+// and phi (rounded to FP32) in LDS slots of its own (registers would spill).
+// The transforms exchange through LDS in FP32 (the arithmetic stays FP64):
+// with x and phi that keeps a workgroup at 80 KB, two per CU.  Each rounding
+// is of the size of the complex64 field store between kernels.  Sums over
+// the polarisations are formed across the lane pair, lower lane first.
 // ---------------------------------------------------------------------------
 template <int N1, int C, int P, int AMODE>
 __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k3_adj(AdjArgs a) {
   constexpr int T = N1 / 16;
   static_assert(P == 1 || C * T >= 32, "two polarisations need lane pairs");
-  // [P][N1][C] transform exchange, then [16][lanes] the lanes' x
+  // [P][N1][C] transform exchange, then [16][lanes] the lanes' x and phi
   extern __shared__ __align__(16) unsigned char lds_adj[];
   float2* lds = reinterpret_cast<float2*>(lds_adj);
   float2* xl = lds + P * N1 * C;
+  float* pl = reinterpret_cast<float*>(xl + P * N1 * C);  // [16][lanes] the lanes' phase
   const int tid = threadIdx.x;
   int p, c, j;
   if constexpr (P == 2) {
@@ -101,7 +101,10 @@ void k3_adj(AdjArgs a) {
     {
       double phi[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) phi[r] = -a.kappa * pol_sum<P>(norm2(reg[r]));
+      for (int r = 0; r < 16; ++r) {
+        phi[r] = -a.kappa * pol_sum<P>(norm2(reg[r]));
+        pl[r * (P * C * T) + tid] = (float)phi[r];
+      }
       for_each_phasor16(phi, [&](int r, cd e) { reg[r] = cmul(reg[r], e); });
     }
 #pragma unroll
@@ -116,10 +119,7 @@ void k3_adj(AdjArgs a) {
     {
       double phi[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float2 v = xl[r * (P * C * T) + tid];
-        phi[r] = -a.kappa * pol_sum<P>(norm2(cd{(double)v.x, (double)v.y}));
-      }
+      for (int r = 0; r < 16; ++r) phi[r] = (double)pl[r * (P * C * T) + tid];
       // x is read again below rather than held across the phasor (the
       // fence keeps the compiler from merging the two reads, which would
       // spill)
@@ -256,7 +256,8 @@ static hipError_t prepare_k3_adj_stored() {
 
 template <int N1, int C, int P>
 constexpr size_t adj_lds_bytes() {
-  return (size_t)2 * P * N1 * C * sizeof(float2);  // exchange + the lanes' x
+  // exchange, the lanes' x and phi
+  return (size_t)2 * P * N1 * C * sizeof(float2) + (size_t)P * N1 * C * sizeof(float);
 }
 
 template <int N1, int C, int P, int AMODE>
@@ -278,7 +279,7 @@ static hipError_t prepare_k3_adj() {
 }
 
 // adjoint column tiles: the forward pass's wide tile (8 columns, 4 at
-// N1 = 512; 64 KB of LDS), state then cotangent
+// N1 = 512; 80 KB of LDS), state then cotangent
 template <int N1, int P>
 static void fill_adj(KernelSet& ks) {
   constexpr int C = N1 == 512 ? 4 : 8;
