@@ -19,14 +19,15 @@ namespace L = ssfm::ldbp;
 
 namespace {
 
-// Tile geometry.  Forward: tiles of up to 1024 samples, up to 20 fused steps
-// per launch (halo 7 per step).  Backward: tiles of up to 512 samples, one
-// span per launch.  SSFM_LDBP_FWD_TILE / SSFM_LDBP_FWD_STEPS /
-// SSFM_LDBP_BWD_TILE override them (powers of two; for tuning).
+// Tile geometry.  Forward: tiles of up to 1024 samples, up to 10 fused steps
+// per launch (halo 7 per step).  Backward: one span per launch over regions
+// of 1024 samples (tile plus halo: four whole waves of R samples per lane).
+// SSFM_LDBP_FWD_TILE / SSFM_LDBP_FWD_STEPS / SSFM_LDBP_BWD_REGION override
+// them (powers of two; for tuning).
 constexpr int kFwdTile = 1024;
-constexpr int kFwdSteps = 20;
-constexpr int kBwdTile = 512;
-constexpr int kFwdMaxRegion = 512 * L::R;  // forward workgroup <= 1024 lanes (512 per polarisation)
+constexpr int kFwdSteps = 10;
+constexpr int kBwdRegion = 1024;
+constexpr int kFwdMaxRegion = 512 * L::R;  // forward workgroup <= 512 lanes
 constexpr int kBwdMaxRegion = 256 * L::R;  // backward workgroup <= 256 lanes
 constexpr int kLossSymbols = 256;          // symbols per loss workgroup
 constexpr int kMfSamples = 512;            // samples per matched-filter-adjoint workgroup
@@ -47,7 +48,9 @@ struct Geometry {
   size_t lds = 0;
 };
 
-Geometry make_geometry(int64_t n, int tile, int halo, int arrays, int n_pol, int extra_lds) {
+// slot: bytes of one LDS sample slot (FP64 complex in the forward, FP32
+// complex in the backward)
+Geometry make_geometry(int64_t n, int tile, int halo, int arrays, int n_pol, size_t slot) {
   Geometry g;
   g.w = (int)std::min<int64_t>(n, tile);
   g.halo = halo;
@@ -55,7 +58,7 @@ Geometry make_geometry(int64_t n, int tile, int halo, int arrays, int n_pol, int
   g.ls = L::region_stride(g.region);
   g.tiles = (int)((n + g.w - 1) / g.w);  // the last tile of a row may be shorter
   g.threads = round_up(g.region / L::R, 64);
-  g.lds = (size_t)arrays * n_pol * g.ls * sizeof(cd) + (size_t)extra_lds;
+  g.lds = (size_t)arrays * n_pol * g.ls * slot;
   return g;
 }
 
@@ -86,7 +89,7 @@ bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
 struct ssfm_ldbp_s {
   ssfm_ldbp_desc d{};
   int device = 0;
-  int fwd_tile = kFwdTile, fwd_steps = kFwdSteps, bwd_tile = kBwdTile;
+  int fwd_tile = kFwdTile, fwd_steps = kFwdSteps, bwd_region = kBwdRegion;
   // workspace: padded taps [K][15], then a region sized for the largest call
   cd* taps15 = nullptr;
   unsigned char* ws = nullptr;
@@ -100,18 +103,15 @@ struct ssfm_ldbp_s {
     return std::max(s, fwd_steps / s * s);
   }
   Geometry fwd_geom(int steps) const {
-    // one polarisation per lane, plus the |y|^2 exchange buffer
-    Geometry g = make_geometry(d.n_samples, fwd_tile, L::HC * steps, 1, d.n_pol, 0);
-    g.threads *= d.n_pol;
-    g.lds += (size_t)d.n_pol * g.region * sizeof(double);
-    return g;
+    // every polarisation of R samples per lane
+    return make_geometry(d.n_samples, fwd_tile, L::HC * steps, 1, d.n_pol, sizeof(cd));
   }
   Geometry bwd_geom() const {
     const int s = d.steps_per_span;
     const int halo = L::HC * std::max(s, 2 * (s - 1));
-    // (tiles of bwd_tile - 2 halo, whose regions fill whole waves, measured
-    // slower: two workgroups of two waves per CU instead of two of three)
-    Geometry g = make_geometry(d.n_samples, bwd_tile, halo, s + 1, d.n_pol, 0);
+    // tiles of bwd_region - 2 halo samples, so a region fills whole waves
+    Geometry g = make_geometry(d.n_samples, bwd_region - 2 * halo, halo, s + 1, d.n_pol,
+                               sizeof(float2));
     g.lds += (size_t)(g.threads / 64) * sizeof(double);  // reduction scratch
     return g;
   }
@@ -309,10 +309,10 @@ int ssfm_ldbp_create(const ssfm_ldbp_desc* desc, int hip_device, ssfm_ldbp_t* ou
   h->device = hip_device;
   h->fwd_tile = env_int("SSFM_LDBP_FWD_TILE", kFwdTile);
   h->fwd_steps = env_int("SSFM_LDBP_FWD_STEPS", kFwdSteps);
-  h->bwd_tile = env_int("SSFM_LDBP_BWD_TILE", kBwdTile);
-  if (!pow2(h->fwd_tile) || !pow2(h->bwd_tile)) {
+  h->bwd_region = env_int("SSFM_LDBP_BWD_REGION", kBwdRegion);
+  if (!pow2(h->fwd_tile) || !pow2(h->bwd_region) || h->bwd_region < 256) {
     delete h;
-    return api_fail(SSFM_EINVAL, "ldbp tile overrides must be powers of two");
+    return api_fail(SSFM_EINVAL, "ldbp tile overrides must be powers of two (region >= 256)");
   }
   // the largest forward launch and the backward launch must fit a workgroup
   const Geometry gf = h->fwd_geom(h->fwd_chunk());

@@ -4,16 +4,19 @@
 // polarisations) with a Kerr phase rotation.  A workgroup owns a tile of w
 // samples of one realisation plus a halo on each side: one step needs 7
 // neighbours per side, so a launch fusing q steps carries a halo of 7 q and
-// never exchanges data with other workgroups.  The tile's state lives in LDS
-// in FP64; each lane owns R = 4 consecutive samples and reads the 18-sample
-// window of its 4 outputs from LDS into registers (4.5 LDS reads per output
-// instead of 15).  HBM sees the state once per launch.
+// never exchanges data with other workgroups.  Each lane owns R = 4
+// consecutive samples of every polarisation and reads the 18-sample window of
+// its 4 outputs from LDS into registers (4.5 LDS reads per output instead of
+// 15).  HBM sees the state once per launch.  The forward keeps the tile's
+// state in LDS in FP64; the backward keeps its recomputed states and the
+// gradient in FP32 (each rounding of the size of the complex64 field store),
+// which halves its LDS and doubles the workgroups a CU holds.
 //
 // LDS slot of sample i: j + floor(j / 4), j = i + 8 -- one pad slot per 4
 // samples.  For the lane owning samples 4 l .. 4 l + 3 the slot of window
 // sample d is 5 l + (a constant of d), so a window is one base address plus
-// immediate offsets, and the 8 lanes of one 128-byte LDS access fall on 8
-// different 16-byte bank groups for every d.
+// immediate offsets, and the lanes of one LDS access fall on distinct banks
+// for every d (a lane stride of 80 bytes in FP64, 40 in FP32).
 //
 // Backward: one launch per span (steps [k0, k0 + S)).  The span's inner
 // states are recomputed from its start checkpoint with the forward code
@@ -75,8 +78,11 @@ __device__ __forceinline__ cd phasor64(double phi) {
   pc = fma(pc, r2, -0.5);
   const double cs = fma(pc, r2, 1.0);
   const int quad = (int)(((long long)q) & 3);
-  // e^{i(r + quad pi/2)} = i^quad e^{ir}
-  return quad == 0 ? cd{cs, sn} : quad == 1 ? cd{-sn, cs} : quad == 2 ? cd{-cs, -sn} : cd{sn, -cs};
+  // e^{i(r + quad pi/2)} = i^quad e^{ir}: (cs, sn), (-sn, cs), (-cs, -sn),
+  // (sn, -cs) for quad = 0..3, formed with selects (no branch)
+  const double re = (quad & 1) ? sn : cs;
+  const double im = (quad & 1) ? cs : sn;
+  return {((quad + 1) & 2) ? -re : re, (quad & 2) ? -im : im};
 }
 
 // Step k's filter from the padded [K][15] copy (uniform loads: the taps
@@ -91,22 +97,26 @@ __device__ __forceinline__ void load_taps(const cd* __restrict__ taps15, int k, 
 // slot map is affine there), so every LDS access is one base register plus
 // an immediate.
 static_assert(R == 4 && GUARD % 4 == 0, "affine lane addressing needs R = 4");
-__device__ __forceinline__ const cd* lane_base(const cd* a, int q) { return a + 5 * q; }
-__device__ __forceinline__ cd* lane_base(cd* a, int q) { return a + 5 * q; }
+template <typename L>
+__device__ __forceinline__ const L* lane_base(const L* a, int q) { return a + 5 * q; }
+template <typename L>
+__device__ __forceinline__ L* lane_base(L* a, int q) { return a + 5 * q; }
 // window sample d (= sample 4 l - HC + d)
 constexpr int win_off(int d) { return (d + GUARD - HC) + ((d + GUARD - HC) >> 2); }
 // own sample r (= sample 4 l + r)
 constexpr int own_off(int r) { return (r + GUARD) + ((r + GUARD) >> 2); }
 
 // Window sample d of the lane owning samples base = 4 q ..: a[base - HC + d].
-__device__ __forceinline__ cd window_at(const cd* a, int q, int d) {
-  return lane_base(a, q)[win_off(d)];
+template <typename L>
+__device__ __forceinline__ cd window_at(const L* a, int q, int d) {
+  return lds_get<cd>(lane_base(a, q) + win_off(d));
 }
 
 // y[r] = sum_t h[t] a[base + r + HC - t]: the FIR step at the lane's samples.
 // The window is streamed: each of its R + 14 samples updates the outputs that
 // use it and is dropped, so only the outputs stay live.
-__device__ __forceinline__ void fir_own(const cd* a, int q, const cd (&h)[TAPS], cd (&y)[R]) {
+template <typename L>
+__device__ __forceinline__ void fir_own(const L* a, int q, const cd (&h)[TAPS], cd (&y)[R]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) y[r] = cd{0.0, 0.0};
 #pragma unroll
@@ -137,8 +147,8 @@ __device__ __forceinline__ void kerr(cd (&y)[P][R], double xi) {
 // One forward step at the lane's samples (both polarisations), reading state
 // array st: the forward kernel's arithmetic, bit for bit (the power is the
 // same single add of the two per-polarisation terms).
-template <int P>
-__device__ __forceinline__ void step_own(const cd* st, int ls, int q,
+template <int P, typename L>
+__device__ __forceinline__ void step_own(const L* st, int ls, int q,
                                          const cd* __restrict__ taps15, const double* __restrict__ xi,
                                          int k, cd (&y)[P][R]) {
   cd h[TAPS];
@@ -155,31 +165,28 @@ __device__ __forceinline__ void step_own(const cd* st, int ls, int q,
 
 // Zero the guard slots of `arrays` consecutive LDS arrays of stride ls
 // holding a region of `region` samples.
-__device__ __forceinline__ void zero_guards(cd* a, int arrays, int ls, int region) {
+template <typename L>
+__device__ __forceinline__ void zero_guards(L* a, int arrays, int ls, int region) {
   for (int q = threadIdx.x; q < arrays * 2 * GUARD; q += blockDim.x) {
     const int arr = q / (2 * GUARD), e = q % (2 * GUARD);
     const int i = e < GUARD ? e - GUARD : region + (e - GUARD);
-    a[arr * ls + lslot(i)] = cd{0.0, 0.0};
+    lds_put(a + arr * ls + lslot(i), cd{0.0, 0.0});
   }
 }
 
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-// One polarisation per lane: lanes [p Q, (p + 1) Q) own polarisation p (Q a
-// multiple of 64, so every wave is one polarisation and its window reads
-// stay conflict-free).  The Kerr step couples the polarisations through
-// |y_q|^2, exchanged in LDS; the sum is one add of the two terms
-// (commutative), so both lanes of a sample rotate by the same phase.
+// Every lane carries its R samples of all polarisations (the backward's
+// step_own, so a recomputed state is bitwise the forward's): the Kerr phase
+// is formed once per sample, in the lane, and the polarisations need no
+// exchange.
 template <int P>
-__global__ __launch_bounds__(1024) void ldbp_fwd(FwdArgs a, const cd* __restrict__ taps15,
-                                                  const double* __restrict__ xi) {
+__global__ __launch_bounds__(512) void ldbp_fwd(FwdArgs a, const cd* __restrict__ taps15,
+                                                 const double* __restrict__ xi) {
   extern __shared__ __align__(16) unsigned char smem_f[];
-  cd* st = reinterpret_cast<cd*>(smem_f);                   // [P][ls]
-  double* pwb = reinterpret_cast<double*>(st + P * a.ls);   // [P][region]
+  cd* st = reinterpret_cast<cd*>(smem_f);  // [P][ls]
   const int tid = threadIdx.x;
-  const int Q = blockDim.x / P;
-  const int p = tid / Q, q = tid % Q;
   const int64_t b = blockIdx.x / a.tiles;
   const int tile = (int)(blockIdx.x % a.tiles);
   const int64_t n0 = (int64_t)tile * a.w - a.halo;
@@ -193,34 +200,24 @@ __global__ __launch_bounds__(1024) void ldbp_fwd(FwdArgs a, const cd* __restrict
       st[pp * a.ls + lslot(i)] = load_c64(src + pp * a.n + ((n0 + i) & nm));
   }
   __syncthreads();
-  const int base = q * R;
-  const bool active = base < a.region;
-  cd* mine = st + p * a.ls;
+  const bool active = tid * R < a.region;
   for (int k = a.k0; k < a.k1; ++k) {
-    cd y[R];
-    double pw[R];
-    if (active) {
-      cd h[TAPS];
-      load_taps(taps15, k, h);
-      fir_own(mine, q, h, y);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        pw[r] = norm2(y[r]);
-        if constexpr (P == 2) pwb[p * a.region + base + r] = pw[r];
-      }
-    }
-    __syncthreads();  // every window of this step is read; |y|^2 published
+    cd y[P][R];
+    if (active) step_own<P>(st, a.ls, tid, taps15, xi, k, y);
+    __syncthreads();  // every window of this step is read
+    // the state at a span boundary is the complex64 field
     const bool span_end = (k + 1) % a.spans_steps == 0;
     if (active) {
-      const double x = xi[k];
+      if (span_end) {  // uniform over the workgroup
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        double tot = pw[r];
-        if constexpr (P == 2) tot = tot + pwb[(1 - p) * a.region + base + r];
-        cd v = cmul(y[r], phasor64(x * tot));
-        // the state at a span boundary is the complex64 field
-        if (span_end) v = round_c64(v);
-        lane_base(mine, q)[own_off(r)] = v;
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int r = 0; r < R; ++r) lane_base(st + p * a.ls, tid)[own_off(r)] = round_c64(y[p][r]);
+      } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int r = 0; r < R; ++r) lane_base(st + p * a.ls, tid)[own_off(r)] = y[p][r];
       }
     }
     __syncthreads();
@@ -294,8 +291,8 @@ __device__ __forceinline__ void block_sum1(double v, double* red, double* out) {
 // contiguous chunk of samples with a sliding 5-sample window of x (two LDS
 // reads per sample for five complex multiply-adds), and the wave reduces
 // its 10 values and writes them to part[10 g ..] (lanes 0..9).
-template <int P>
-__device__ __forceinline__ void tap_gradient(const cd* G, const cd* X, int ls, int halo, int w,
+template <int P, typename L>
+__device__ __forceinline__ void tap_gradient(const L* G, const L* X, int ls, int halo, int w,
                                              double* part) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
@@ -308,17 +305,17 @@ __device__ __forceinline__ void tap_gradient(const cd* G, const cd* X, int ls, i
     const int t0 = 5 * grp;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const cd* Gp = G + p * ls;
-      const cd* Xp = X + p * ls;
+      const L* Gp = G + p * ls;
+      const L* Xp = X + p * ls;
       // xw[u] = x[n + c - t0 - u]
       cd xw[5];
 #pragma unroll
-      for (int u = 0; u < 5; ++u) xw[u] = Xp[lslot(n0 - 1 + HC - t0 - u)];
+      for (int u = 0; u < 5; ++u) xw[u] = lds_get<cd>(Xp + lslot(n0 - 1 + HC - t0 - u));
       for (int n = n0; n < n1; ++n) {
 #pragma unroll
         for (int u = 4; u > 0; --u) xw[u] = xw[u - 1];
-        xw[0] = Xp[lslot(n + HC - t0)];
-        const cd gv = Gp[lslot(n)];
+        xw[0] = lds_get<cd>(Xp + lslot(n + HC - t0));
+        const cd gv = lds_get<cd>(Gp + lslot(n));
 #pragma unroll
         for (int u = 0; u < 5; ++u) {
           v[2 * u] = fma(gv.re, xw[u].re, fma(gv.im, xw[u].im, v[2 * u]));
@@ -340,9 +337,9 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
                                                  const double* __restrict__ xis) {
   extern __shared__ __align__(16) unsigned char smem_b[];
   // [X_0 .. X_{S-1}][G] states and gradient, P * ls each, then the reduction
-  cd* xs_lds = reinterpret_cast<cd*>(smem_b);
+  float2* xs_lds = reinterpret_cast<float2*>(smem_b);
   const int plane = P * a.ls;
-  cd* G = xs_lds + a.s_steps * plane;
+  float2* G = xs_lds + a.s_steps * plane;
   double* red = reinterpret_cast<double*>(G + plane);
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x / a.tiles;
@@ -356,7 +353,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
   for (int i = tid; i < a.region; i += blockDim.x) {
 #pragma unroll
     for (int p = 0; p < P; ++p)
-      xs_lds[p * a.ls + lslot(i)] = load_c64(a.x0 + row0 + p * a.n + ((n0 + i) & nm));
+      xs_lds[p * a.ls + lslot(i)] = a.x0[row0 + p * a.n + ((n0 + i) & nm)];
   }
   const int base = tid * R;
   const bool active = base < a.region;
@@ -369,7 +366,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) lane_base(xs_lds + j * plane + p * a.ls, tid)[own_off(r)] = y[p][r];
+        for (int r = 0; r < R; ++r) lds_put(lane_base(xs_lds + j * plane + p * a.ls, tid) + own_off(r), y[p][r]);
     }
     __syncthreads();
   }
@@ -389,12 +386,13 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
   for (int j = a.s_steps - 1; j >= 0; --j) {
     const int k = a.k0 + j;
     const double xi = xis[k];
-    const cd* X = xs_lds + j * plane;
+    const float2* X = xs_lds + j * plane;
     if (j < a.s_steps - 1 && active) {
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) z[p][r] = lane_base(xs_lds + (j + 1) * plane + p * a.ls, tid)[own_off(r)];
+        for (int r = 0; r < R; ++r)
+          z[p][r] = lds_get<cd>(lane_base(xs_lds + (j + 1) * plane + p * a.ls, tid) + own_off(r));
     }
     // Kerr pullback at the lane's samples (z = output, g = its gradient)
     double xi_part = 0.0;
@@ -424,9 +422,12 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) lane_base(G + p * a.ls, tid)[own_off(r)] = gy[p][r];
+        for (int r = 0; r < R; ++r) lds_put(lane_base(G + p * a.ls, tid) + own_off(r), gy[p][r]);
     }
     __syncthreads();
+    // the tap gradient first: nothing else is live in the registers then
+    double* part = a.partial + ((int64_t)k * gridDim.x + blockIdx.x) * NRED;
+    tap_gradient<P>(G, X, a.ls, a.halo, wt, part);
     // FIR pullback at the lane's samples: gx[m] = sum_t conj(h[t]) gy[m - c + t]
     if (active) {
       cd h[TAPS];
@@ -447,8 +448,6 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
         }
       }
     }
-    double* part = a.partial + ((int64_t)k * gridDim.x + blockIdx.x) * NRED;
-    tap_gradient<P>(G, X, a.ls, a.halo, wt, part);
     // dL/dxi: one value, summed over the workgroup
     block_sum1(xi_part, red, part + 2 * TAPS);
   }
