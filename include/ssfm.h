@@ -284,8 +284,8 @@ typedef struct ssfm_tune_info {
 } ssfm_tune_info;
 
 /* Choose the launch shape of the four-step path for `batch` realisations by
- * measurement: each combination of column tile (narrow: 2 columns; wide: 8,
- * or 4 at N1 = 512) and row workgroup (narrow: 64 lanes; wide: 256) runs a
+ * measurement: each combination of column tile (narrow: 2 columns; wide: 8)
+ * and row workgroup (narrow: 64 lanes; wide: 256) runs a
  * few split steps (row pass + nonlinear column pass) on a scratch field on
  * `stream`, timed with HIP events, and the fastest is recorded in the plan
  * for this batch size.  Later forward calls with this batch use it (the

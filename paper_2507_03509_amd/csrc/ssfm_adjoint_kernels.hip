@@ -278,11 +278,11 @@ static hipError_t prepare_k3_adj() {
   return hipSuccess;
 }
 
-// adjoint column tiles: the forward pass's wide tile (8 columns, 4 at
-// N1 = 512; 80 KB of LDS), state then cotangent
+// adjoint column tiles: the forward pass's wide tile (8 columns; 80 KB of
+// LDS), state then cotangent
 template <int N1, int P>
 static void fill_adj(KernelSet& ks) {
-  constexpr int C = N1 == 512 ? 4 : 8;
+  constexpr int C = 8;
   ks.adj[AMODE_FIRST] = &launch_k3_adj<N1, C, P, AMODE_FIRST>;
   ks.adj[AMODE_NL] = &launch_k3_adj<N1, C, P, AMODE_NL>;
   ks.adj[AMODE_LAST] = &launch_k3_adj<N1, C, P, AMODE_LAST>;
@@ -291,8 +291,8 @@ static void fill_adj(KernelSet& ks) {
                        prepare_k3_adj<N1, C, P, AMODE_LAST>()})
     if (e != hipSuccess) ks.prepare = e;
   // cotangent-only tiles with stored states: the forward column pass's wide
-  // tile (8 columns, 4 at N1 = 512; 64 KB of FP64 LDS)
-  constexpr int CS = N1 == 512 ? 4 : 8;
+  // tile (8 columns; 64 KB of FP64 LDS)
+  constexpr int CS = 8;
   ks.adj_stored = &launch_k3_adj_stored<N1, CS, P>;
   const hipError_t e = prepare_k3_adj_stored<N1, CS, P>();
   if (e != hipSuccess) ks.prepare = e;
@@ -302,7 +302,6 @@ void select_adjoint_kernels(int n1, int n_pol, KernelSet& ks) {
   switch (n1) {
     case 128: if (n_pol == 1) fill_adj<128, 1>(ks); else fill_adj<128, 2>(ks); break;
     case 256: if (n_pol == 1) fill_adj<256, 1>(ks); else fill_adj<256, 2>(ks); break;
-    case 512: if (n_pol == 1) fill_adj<512, 1>(ks); else fill_adj<512, 2>(ks); break;
     default: break;
   }
 }

@@ -124,7 +124,7 @@ struct KernelSet {
   LdsDftLaunch lds_dft[2] = {nullptr, nullptr};  // the LDS-resident transform: forward, inverse
   RowLaunch row_wide = nullptr, row_narrow = nullptr;
   int rows_wide = 0, rows_narrow = 0;  // rows per workgroup
-  // column tiles: narrow (2 columns) and wide (8, or 4 at N1 = 512)
+  // column tiles: narrow (2 columns) and wide (8)
   FourStepKernels narrow, wide;
   AdjLaunch adj[3] = {nullptr, nullptr, nullptr};
   int adj_columns = 0;

@@ -665,12 +665,12 @@ static void fill_k3(FourStepKernels& k) {
 }
 
 // FFT exchanges in FP64 LDS (FP32 for the FP32 variant), 64 KB per workgroup
-// for the wide FP64 tiles: 8 (4 at N1 = 512) adjacent columns, 64/32-byte row
-// segments; narrow tiles: 2 columns, for batches too small to fill the chip
+// for the wide FP64 tiles: 8 adjacent columns, 64-byte row segments; narrow
+// tiles: 2 columns, for batches too small to fill the chip
 template <int N1, int P, typename R>
 static void fill_cols(KernelSet& ks) {
   using L = std::conditional_t<sizeof(R) == 8, cd, float2>;
-  fill_k3<N1, N1 == 512 ? 4 : 8, P, L, R>(ks.wide);
+  fill_k3<N1, 8, P, L, R>(ks.wide);
   fill_k3<N1, 2, P, L, R>(ks.narrow);
 }
 
@@ -727,7 +727,10 @@ static bool select_kernels_t(int64_t n, int n_pol, KernelSet& ks) {
     }
   }
   ks.path = 2;
-  const int l1 = l / 2;
+  // N1 x N2 with N1 <= N2 and N1 <= 256: 2^18 = 256 x 1024 (the 8-column
+  // tiles of the 256-row column pass and its two FFT passes; 512 x 512 with
+  // 4-column tiles and three passes measured 18 % slower on workload 3)
+  const int l1 = l == 18 ? 8 : l / 2;
   ks.n1 = 1 << l1;
   ks.n2 = (int)(n >> l1);
   hipError_t pr = hipSuccess;
@@ -735,6 +738,7 @@ static bool select_kernels_t(int64_t n, int n_pol, KernelSet& ks) {
     case 128: pr = fill_rows<128, R>(ks); break;
     case 256: pr = fill_rows<256, R>(ks); break;
     case 512: pr = fill_rows<512, R>(ks); break;
+    case 1024: pr = fill_rows<1024, R>(ks); break;
     default: return false;
   }
   if (pr != hipSuccess) ks.prepare = pr;
@@ -746,10 +750,6 @@ static bool select_kernels_t(int64_t n, int n_pol, KernelSet& ks) {
     case 256:
       if (n_pol == 1) { fill_cols<256, 1, R>(ks); }
       else { fill_cols<256, 2, R>(ks); }
-      break;
-    case 512:
-      if (n_pol == 1) { fill_cols<512, 1, R>(ks); }
-      else { fill_cols<512, 2, R>(ks); }
       break;
     default: return false;
   }

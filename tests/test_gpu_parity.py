@@ -301,8 +301,9 @@ def test_two_stream_split_is_bitwise(ssfm, n, batch):
 
 # ---------------------------------------------------------------------------
 # the wide launch shapes of the longest fields: a batch large enough that
-# the heuristic picks the wide column tile (8 columns at N1 = 256, 4 at
-# N1 = 512) and the 256-lane row workgroup of the 512-point rows
+# the heuristic picks the wide column tile (8 columns at N1 = 256) and the
+# 256-lane row workgroup of the 512- and 1024-point rows (2^17 = 256 x 512,
+# 2^18 = 256 x 1024)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n_pol", [1, 2])
@@ -314,7 +315,7 @@ def test_wide_tiles_long_fields(ssfm, n, n_pol):
     plan = ssfm.Plan(ln)
     info = plan.info
     plan.close()
-    assert info["n2"] == 512
+    assert (info["n1"], info["n2"]) == (256, n // 256)
     assert batch * (info["n2"] // info["columns_per_tile"]) >= 512  # wide tiles
     a0 = qam(n_pol, n, seed=n + 7 * n_pol, batch=batch)
     got = run_gpu(ssfm, a0, ln, seed=12)
