@@ -101,8 +101,18 @@ typedef struct ssfm_plan_info {
   int32_t n1;                /* four-step: column FFT length (0 for path 1)   */
   int32_t n2;                /* four-step: row FFT length (0 for path 1)      */
   int32_t columns_per_tile;  /* four-step: column-tile width at batch >= 8    */
-  int64_t launches_per_call; /* kernel launches of one ssfm_forward call      */
+  int64_t launches_per_call; /* kernel launches of one ssfm_forward call of  *
+                              * at most chunk_realisations realisations       */
   int64_t table_bytes;       /* device memory owned by the plan               */
+  int64_t chunk_realisations; /* four-step: the most realisations a forward   *
+                              * call carries through the link at a time:     *
+                              * larger batches run as equal chunks, one      *
+                              * after the other, each about 256 MiB (the     *
+                              * Infinity Cache; SSFM_CHUNK_MIB in the        *
+                              * environment at plan creation sets another    *
+                              * size, 0 none); the adjoint's chunks are half *
+                              * as large (two fields).  0 for path 1 or      *
+                              * without chunks                               */
 } ssfm_plan_info;
 
 /* Build a plan for `link` on HIP device `hip_device`.
@@ -124,7 +134,10 @@ int ssfm_plan_get_info(ssfm_plan_t plan, ssfm_plan_info* info);
  *   field:  device pointer to complex64 [batch][n_pol][n_samples], 8-byte
  *           aligned, owned by the caller; overwritten with the output.
  *   batch:  >= 1.  Realisation r of the batch draws its noise with key
- *           (seed, r * 2^16 + span).
+ *           (seed, r * 2^16 + span).  On the four-step path a batch above
+ *           the plan's chunk_realisations (ssfm_plan_info) runs as equal
+ *           chunks through the whole link, one after the other, with the
+ *           same bits as one pass over the batch.
  *   stream: hipStream_t to order the work on (NULL = default stream).
  * Asynchronous with respect to the host: returns once the kernels are
  * enqueued; a fault inside a kernel surfaces at the caller's next
@@ -176,7 +189,7 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
  * chain rule in Wirtinger calculus for y = x exp(i coef sum|x|^2).
  * Kept spans: with a state budget set (ssfm_plan_set_state_memory), the
  * forward pass also stores the input x of every nonlinear step of the last
- * K spans (K = the number of whole spans of steps_per_span * batch * n_pol *
+ * K spans (K = the number of whole spans of steps_per_span * chunk * n_pol *
  * n_samples * 8 bytes that the budget holds, at most n_spans), rounded to
  * complex64; the reverse sweep of those spans carries the cotangent alone
  * and takes x from the store (y = x e^{i phi}, phi = coef sum|x|^2).  The
@@ -187,9 +200,17 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
  * the input x of each nonlinear step, and the cotangent is pulled back
  * through it (amplifier, then per step the linear step's adjoint and the
  * nonlinear pullback with x); the state budget does not apply.
- * Workspace: four-step path (n_spans + 2) * batch * n_pol * n_samples * 8
- * bytes plus the kept spans' states; LDS-resident path (n_spans +
- * steps_per_span) * batch * n_pol * n_samples * 8 bytes; allocated on first
+ * Chunks: on the four-step path a batch above half the plan's
+ * chunk_realisations (ssfm_plan_info) runs as equal chunks, one after the
+ * other, each through the whole method above on the workspace of one chunk,
+ * with the state budget applied per chunk (so a chunk may keep more spans
+ * than a whole-batch pass would); without kept spans the bits are those of
+ * one pass over the batch.
+ * Workspace: four-step path (n_spans + 2) * chunk * n_pol * n_samples * 8
+ * bytes (chunk = the batch, or its chunk size) plus the kept spans' states
+ * (steps_per_span * chunk * n_pol * n_samples * 8 bytes per span);
+ * LDS-resident path (n_spans + steps_per_span) * batch * n_pol * n_samples *
+ * 8 bytes; allocated on first
  * use (and grown) and owned by the plan; if the device refuses the states'
  * allocation, fewer spans are kept.
  * Calls on one plan are serialised, since they share that workspace: on the

@@ -76,6 +76,7 @@ class SsfmPlanInfo(ctypes.Structure):
         ("columns_per_tile", ctypes.c_int32),
         ("launches_per_call", ctypes.c_int64),
         ("table_bytes", ctypes.c_int64),
+        ("chunk_realisations", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -42,7 +42,7 @@ def test_struct_layout_matches_header():
     import ctypes
     assert ctypes.sizeof(ssfm.SsfmLink) == 104
     assert ssfm.SsfmLink.n_samples.offset == 16
-    assert ctypes.sizeof(ssfm.SsfmPlanInfo) == 32
+    assert ctypes.sizeof(ssfm.SsfmPlanInfo) == 40
 
 
 def test_tune_info_layout_and_null_arguments():
