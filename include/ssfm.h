@@ -201,13 +201,16 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
  * through it (amplifier, then per step the linear step's adjoint and the
  * nonlinear pullback with x); the state budget does not apply.
  * Chunks: on the four-step path a batch above half the plan's
- * chunk_realisations (ssfm_plan_info) runs as equal chunks, one after the
- * other, each through the whole method above on the workspace of one chunk,
- * with the state budget applied per chunk (so a chunk may keep more spans
- * than a whole-batch pass would); without kept spans the bits are those of
- * one pass over the batch.
- * Workspace: four-step path (n_spans + 2) * chunk * n_pol * n_samples * 8
- * bytes (chunk = the batch, or its chunk size) plus the kept spans' states
+ * chunk_realisations (ssfm_plan_info) runs as equal chunks of two-field
+ * working sets.  Without kept spans, the forward pass runs first over the
+ * whole batch (in the forward's chunks), keeping every realisation's span
+ * checkpoints, then the reverse sweep runs chunk by chunk; the bits are
+ * those of one pass over the batch.  With a state budget each chunk's whole
+ * adjoint runs on the workspace of one chunk, the budget applied per chunk
+ * (so a chunk may keep more spans than a whole-batch pass would).
+ * Workspace: four-step path n_spans * batch * n_pol * n_samples * 8 bytes
+ * of checkpoints (n_spans * chunk * ... with a state budget) and a work
+ * buffer of two chunks' fields, plus the kept spans' states
  * (steps_per_span * chunk * n_pol * n_samples * 8 bytes per span);
  * LDS-resident path (n_spans + steps_per_span) * batch * n_pol * n_samples *
  * 8 bytes; allocated on first

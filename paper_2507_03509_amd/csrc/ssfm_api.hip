@@ -428,7 +428,7 @@ bool use_graphs(const ssfm_plan_s* p) {
 int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uint64_t real0,
                 int s0, int s1, hipStream_t st, float2* ckpt = nullptr,
                 const uint64_t* seeds = nullptr, float2* states = nullptr,
-                int state_span0 = 0) {
+                int state_span0 = 0, size_t ckpt_stride = 0) {
   const ssfm::KernelSet& ks = p->ks;
   hipError_t e;
   if (s0 == s1) return SSFM_OK;
@@ -498,7 +498,10 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
         }
       } else {
         mode = s + 1 < s1 ? ssfm::MODE_EDFA : ssfm::MODE_LAST;
-        a.ckpt = ckpt ? ckpt + (size_t)s * batch * p->n_pol * p->n : nullptr;
+        // span s's checkpoints: ckpt_stride elements apart (default: the batch)
+        a.ckpt = ckpt ? ckpt + (size_t)s * (ckpt_stride ? ckpt_stride
+                                                        : (size_t)batch * p->n_pol * p->n)
+                      : nullptr;
       }
       // a stored nonlinear-step input is one more write of the field
       const double bytes = mode == ssfm::MODE_NL_STORE ? 1.5 * field_bytes : field_bytes;
@@ -882,26 +885,32 @@ int run_split(ssfm_plan_s* p, hipStream_t st, F&& part) {
   return SSFM_OK;
 }
 
-// The adjoint of `batch` realisations (noise indices real0 + b) on stream st,
-// with the workspace regions of this (sub-)batch: work [2 batch] fields,
-// ckpt [spans][batch], states [kept][steps][batch] (kept trailing spans).
-int run_adjoint(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t batch, uint64_t seed,
-                uint64_t real0, hipStream_t st, float2* work, float2* ckpt, float2* states,
-                int kept) {
+// The adjoint's forward pass over `batch` realisations: the input copied
+// into work, run through the link, keeping the span-end states at ckpt
+// (span s at ckpt + s * ckpt_stride elements; 0: the batch's own slice) and
+// the nonlinear-step inputs of the kept spans.
+int adjoint_forward(ssfm_plan_s* plan, const void* field_in, int64_t batch, uint64_t seed,
+                    uint64_t real0, hipStream_t st, float2* work, float2* ckpt,
+                    size_t ckpt_stride, float2* states, int kept) {
+  const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
+  const hipError_t e =
+      hipMemcpyAsync(work, field_in, slice * sizeof(float2), hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return api_fail_hip(e, "hipMemcpyAsync (adjoint input)");
+  return run_forward(plan, work, batch, seed, real0, 0, plan->spans, st, ckpt, nullptr,
+                     kept > 0 ? states : nullptr, plan->spans - kept, ckpt_stride);
+}
+
+// The adjoint's reverse sweep over `batch` realisations: the cotangent taken
+// from grad and returned there, the state rebuilt from the span checkpoints
+// at ckpt (stride as for adjoint_forward), the kept spans' stored inputs.
+int adjoint_reverse(ssfm_plan_s* plan, void* grad, int64_t batch, hipStream_t st,
+                    float2* work, float2* ckpt, size_t ckpt_stride, float2* states, int kept) {
   const ssfm::KernelSet& ks = plan->ks;
   const size_t slice = (size_t)batch * plan->n_pol * plan->n;  // elements
+  if (!ckpt_stride) ckpt_stride = slice;
   const int kept_span0 = plan->spans - kept;
   float2* cot = work + slice;
   hipError_t e;
-  int rc;
-  // forward pass on a copy of the input, keeping the span-end states (and the
-  // nonlinear-step inputs of the kept spans)
-  if ((e = hipMemcpyAsync(work, field_in, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
-      hipSuccess)
-    return api_fail_hip(e, "hipMemcpyAsync (adjoint input)");
-  rc = run_forward(plan, work, batch, seed, real0, 0, plan->spans, st, ckpt, nullptr,
-                   kept > 0 ? states : nullptr, kept_span0);
-  if (rc != SSFM_OK) return rc;
   if ((e = hipMemcpyAsync(cot, grad, slice * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
     return api_fail_hip(e, "hipMemcpyAsync (cotangent)");
@@ -969,7 +978,7 @@ int run_adjoint(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t bat
       return api_fail_hip(e, "k3 launch (adjoint)");
   }
   for (int s = kept_span0 - 1; s >= 0; --s) {
-    aa.ckpt = ckpt + (size_t)s * slice;
+    aa.ckpt = ckpt + (size_t)s * ckpt_stride;
     if ((e = launch(plan, KIND_ADJ, row_bytes, st,
                     [&] { return ks.adj[ssfm::AMODE_FIRST](aa, st); })) != hipSuccess)
       return api_fail_hip(e, "k3_adj launch");
@@ -993,6 +1002,17 @@ int run_adjoint(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t bat
       hipSuccess)
     return api_fail_hip(e, "hipMemcpyAsync (gradient)");
   return SSFM_OK;
+}
+
+// The whole adjoint of `batch` realisations (noise indices real0 + b) on
+// stream st, with the workspace regions of this (sub-)batch: work [2 batch]
+// fields, ckpt [spans][batch], states [kept][steps][batch].
+int run_adjoint(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t batch, uint64_t seed,
+                uint64_t real0, hipStream_t st, float2* work, float2* ckpt, float2* states,
+                int kept) {
+  const int rc = adjoint_forward(plan, field_in, batch, seed, real0, st, work, ckpt, 0, states, kept);
+  if (rc != SSFM_OK) return rc;
+  return adjoint_reverse(plan, grad, batch, st, work, ckpt, 0, states, kept);
 }
 
 
@@ -1043,13 +1063,26 @@ void adjoint_workspace(const ssfm_plan_s* plan, int64_t batch, size_t* work, siz
 // the previous adjoint call.
 int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t batch,
                        uint64_t seed, hipStream_t st) {
-  // one stream: the batch in sequential chunks sized for two fields (state
-  // and cotangent), each chunk's whole adjoint on the workspace of one chunk
+  // One stream: the batch in sequential chunks sized for two fields (state
+  // and cotangent).  Without kept spans the forward pass first runs over the
+  // whole batch in the forward's one-field chunks, keeping every
+  // realisation's span checkpoints, then the reverse sweep runs chunk by
+  // chunk; with kept spans each chunk's whole adjoint runs on the workspace
+  // of one chunk, the state budget applied per chunk.
   const bool split = plan->ks.path == 2 && forward_parts(plan, batch) > 1;
   const int64_t cb = split ? batch : chunk_batch(plan, batch, 2);
-  const size_t slice = (size_t)cb * plan->n_pol * plan->n;  // elements
+  const int64_t fb = split ? batch : chunk_batch(plan, batch, 1);
+  const size_t elems = (size_t)plan->n_pol * plan->n;
+  const size_t slice = (size_t)cb * elems;
+  const size_t span_state_bytes = (size_t)plan->steps * slice * sizeof(float2);
+  const bool two_phase = plan->ks.path == 2 && !split && cb < batch &&
+                         plan->state_budget < span_state_bytes;
   size_t work_elems, ckpt_elems;
   adjoint_workspace(plan, cb, &work_elems, &ckpt_elems);
+  if (two_phase) {
+    work_elems = std::max(work_elems, (size_t)fb * elems);
+    ckpt_elems = (size_t)plan->spans * batch * elems;
+  }
   const size_t ckpt_bytes = ckpt_elems * sizeof(float2);
   const size_t work_bytes = work_elems * sizeof(float2);
   if (ckpt_bytes > plan->adj_ckpt_bytes || work_bytes > plan->adj_work_bytes) {
@@ -1073,10 +1106,27 @@ int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int6
   }
   if (plan->ks.path == 1)
     return run_adjoint_lds(plan, field_in, grad, batch, seed, st, plan->adj_ckpt, plan->adj_work);
+  if (two_phase) {
+    const size_t stride = (size_t)batch * elems;  // between spans' checkpoints
+    for (int64_t b0 = 0; b0 < batch; b0 += fb) {
+      const size_t o = (size_t)b0 * elems;
+      const int rc = adjoint_forward(plan, static_cast<const float2*>(field_in) + o,
+                                     std::min(fb, batch - b0), seed, (uint64_t)b0, st,
+                                     plan->adj_work, plan->adj_ckpt + o, stride, nullptr, 0);
+      if (rc != SSFM_OK) return rc;
+    }
+    for (int64_t b0 = 0; b0 < batch; b0 += cb) {
+      const size_t o = (size_t)b0 * elems;
+      const int rc = adjoint_reverse(plan, static_cast<float2*>(grad) + o,
+                                     std::min(cb, batch - b0), st, plan->adj_work,
+                                     plan->adj_ckpt + o, stride, nullptr, 0);
+      if (rc != SSFM_OK) return rc;
+    }
+    return SSFM_OK;
+  }
   // trailing spans whose nonlinear-step inputs the forward pass keeps, as
   // many as the plan's state budget holds (grown on demand; an allocation
   // the device refuses lowers the count)
-  const size_t span_state_bytes = (size_t)plan->steps * slice * sizeof(float2);
   int kept = (int)std::min<uint64_t>((uint64_t)plan->spans, plan->state_budget / span_state_bytes);
   if ((size_t)kept * span_state_bytes > plan->adj_states_bytes) {
     if (plan->adj_pending) {
@@ -1099,7 +1149,6 @@ int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int6
   // two concurrent sub-batches (when the plan asks for them) on carved
   // halves of the workspace, else the chunks one after the other
   if (!split) {
-    const size_t elems = (size_t)plan->n_pol * plan->n;
     for (int64_t b0 = 0; b0 < batch; b0 += cb) {
       const size_t o = (size_t)b0 * elems;
       const int rc = run_adjoint(plan, static_cast<const float2*>(field_in) + o,
@@ -1111,7 +1160,6 @@ int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int6
     return SSFM_OK;
   }
   const int64_t b0 = batch / 2;
-  const size_t elems = (size_t)plan->n_pol * plan->n;
   const int64_t sub[2] = {b0, batch - b0};
   const int64_t off[2] = {0, b0};
   return run_split(plan, st, [&](int h, hipStream_t ws) {
