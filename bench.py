@@ -553,7 +553,8 @@ def main() -> int:
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": tr["bytes_per_launch"] if tr else None,
         "kernel": dom["name"], "avg_launch_us": round(per_launch_ms * 1e3, 3),
-        "measured_on": "single-stream calls of the full batch, HIP events around every launch",
+        "measured_on": "single-stream calls of the full batch (run by the library as "
+                       "cache-sized chunks), HIP events around every launch",
         "single_stream_ms_per_call": round(ms_single, 3),
         "path_gbs": round(2 * 2 * batch * p * n * 8 * total_steps / (ms_per_step * 1e-3) / 1e9, 1),
         "algorithmic_bytes_per_launch": bytes_per_launch,
