@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--dft16", action="store_true",
                     help="time the radix-16 DFT stage prototype: the FFTs' vector "
                          "butterfly against the matrix-core product (one JSON line)")
+    ap.add_argument("--launch-events", type=int, default=1,
+                    help="time every launch with HIP events for the roofline and the "
+                         "kernel breakdowns (0: skip them, e.g. under counter collection)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a "
                          "known-size reference for hardware traffic counters)")
@@ -523,46 +526,49 @@ def main() -> int:
     log(f"timed {args.steps} calls: {ms_per_step:.3f} ms/call, wall {wall:.3f}s, "
         f"{value:.4e} sample-steps/s")
 
-    # ---- kernel rates: K single-stream calls with HIP events around every
-    # launch on the launch stream (the events also turn graph replay off) ----
-    plan.set_forward_streams(1)
-    ssfm.ssfm_profile_begin(plan.handle)
-    torch.cuda.synchronize()
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    k0.record(stream)
-    for _ in range(args.steps):
-        plan.forward(field, seed=w.ase_seed, stream=stream)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    stats = ssfm.ssfm_profile_end(plan.handle)
-    plan.set_forward_streams(0)
-    ms_single = k0.elapsed_time(k1) / args.steps
-    log(f"single-stream calls with per-launch events: {ms_single:.3f} ms/call")
-    for s in stats:
-        log(f"  {s['name']}: {s['launches']} launches, {s['total_ms']:.3f} ms, "
-            f"{s['field_bytes'] / (s['total_ms'] * 1e-3) / 1e9:.1f} GB/s algorithmic")
+    if args.launch_events:
+        # ---- kernel rates: K single-stream calls with HIP events around every
+        # launch on the launch stream (the events also turn graph replay off) ----
+        plan.set_forward_streams(1)
+        ssfm.ssfm_profile_begin(plan.handle)
+        torch.cuda.synchronize()
+        k0 = torch.cuda.Event(enable_timing=True)
+        k1 = torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        for _ in range(args.steps):
+            plan.forward(field, seed=w.ase_seed, stream=stream)
+        k1.record(stream)
+        torch.cuda.synchronize()
+        stats = ssfm.ssfm_profile_end(plan.handle)
+        plan.set_forward_streams(0)
+        ms_single = k0.elapsed_time(k1) / args.steps
+        log(f"single-stream calls with per-launch events: {ms_single:.3f} ms/call")
+        for s in stats:
+            log(f"  {s['name']}: {s['launches']} launches, {s['total_ms']:.3f} ms, "
+                f"{s['field_bytes'] / (s['total_ms'] * 1e-3) / 1e9:.1f} GB/s algorithmic")
 
-    dom = max(stats, key=lambda s: s["total_ms"])
-    per_launch_ms = dom["total_ms"] / dom["launches"]
-    bytes_per_launch = dom["field_bytes"] / dom["launches"]
-    achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
-    tr = traffic_record(dom["name"])
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": tr["bytes_per_launch"] if tr else None,
-        "kernel": dom["name"], "avg_launch_us": round(per_launch_ms * 1e3, 3),
-        "measured_on": "single-stream calls of the full batch (run by the library as "
-                       "cache-sized chunks), HIP events around every launch",
-        "single_stream_ms_per_call": round(ms_single, 3),
-        "path_gbs": round(2 * 2 * batch * p * n * 8 * total_steps / (ms_per_step * 1e-3) / 1e9, 1),
-        "algorithmic_bytes_per_launch": bytes_per_launch,
-        "kernels": {s["name"]: {"launches": s["launches"],
-                                "avg_us": round(s["total_ms"] / s["launches"] * 1e3, 3),
-                                "gbs": round(s["field_bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1)}
-                    for s in stats},
-    }
+        dom = max(stats, key=lambda s: s["total_ms"])
+        per_launch_ms = dom["total_ms"] / dom["launches"]
+        bytes_per_launch = dom["field_bytes"] / dom["launches"]
+        achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+        tr = traffic_record(dom["name"])
+        roofline = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": tr["bytes_per_launch"] if tr else None,
+            "kernel": dom["name"], "avg_launch_us": round(per_launch_ms * 1e3, 3),
+            "measured_on": "single-stream calls of the full batch (run by the library as "
+                           "cache-sized chunks), HIP events around every launch",
+            "single_stream_ms_per_call": round(ms_single, 3),
+            "path_gbs": round(2 * 2 * batch * p * n * 8 * total_steps / (ms_per_step * 1e-3) / 1e9, 1),
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "kernels": {s["name"]: {"launches": s["launches"],
+                                    "avg_us": round(s["total_ms"] / s["launches"] * 1e3, 3),
+                                    "gbs": round(s["field_bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1)}
+                        for s in stats},
+        }
+    else:
+        roofline = None
 
     # ---- forward + adjoint (one ssfm_adjoint call: forward with span
     # checkpoints, then the reverse sweep) on the same batch -----------------
@@ -584,13 +590,15 @@ def main() -> int:
                 times.append(a0.elapsed_time(a1))
             ms = sorted(times)[len(times) // 2]  # median
             # per-kernel breakdown of one more call (events around every launch)
-            ssfm.ssfm_profile_begin(plan.handle)
-            plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
-            torch.cuda.synchronize()
-            for s_ in ssfm.ssfm_profile_end(plan.handle):
-                log(f"  adjoint call ({label}) {s_['name']}: {s_['launches']} launches, "
-                    f"{s_['total_ms']:.1f} ms, "
-                    f"{s_['field_bytes'] / (s_['total_ms'] * 1e-3) / 1e9:.1f} GB/s algorithmic")
+            if args.launch_events:
+                ssfm.ssfm_profile_begin(plan.handle)
+                plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
+                torch.cuda.synchronize()
+                for s_ in ssfm.ssfm_profile_end(plan.handle):
+                    log(f"  adjoint call ({label}) {s_['name']}: {s_['launches']} launches, "
+                        f"{s_['total_ms']:.1f} ms, "
+                        f"{s_['field_bytes'] / (s_['total_ms'] * 1e-3) / 1e9:.1f} GB/s "
+                        "algorithmic")
             log(f"forward+adjoint ({label}): median {ms:.3f} ms of {reps} "
                 f"({', '.join(f'{t:.1f}' for t in times)}), {ms / ms_per_step:.2f}x forward")
             return ms, times
@@ -721,9 +729,11 @@ def main() -> int:
     e1.record(stream)
     torch.cuda.synchronize()
     copy_gbs = 2 * field.numel() * 8 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
-    roofline["copy_kernel_gbs"] = round(copy_gbs, 1)
-    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
-    log(f"copy kernel: {copy_gbs:.1f} GB/s (the column pass reaches {achieved / copy_gbs:.2f} of it)")
+    if roofline is not None:
+        roofline["copy_kernel_gbs"] = round(copy_gbs, 1)
+        roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+        log(f"copy kernel: {copy_gbs:.1f} GB/s (the column pass reaches "
+            f"{achieved / copy_gbs:.2f} of it)")
     del dst
 
     # ---- CPU oracle on one realisation (also the parity reference) ----------
