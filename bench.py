@@ -618,7 +618,9 @@ def main() -> int:
                "fwd_adjoint_ms": round(ms_rebuild, 3),
                "ratio_to_forward": round(ms_rebuild / ms_per_step, 3),
                "timed_calls_ms": [round(t, 3) for t in t_rebuild],
-               "workspace_gib": round((link.n_spans + 2) * cb * p * n * 8 / 2 ** 30, 2),
+               # span checkpoints of the whole batch (the forward pass runs
+               # over all chunks first) and a two-chunk work buffer
+               "workspace_gib": round((link.n_spans * batch + 2 * cb) * p * n * 8 / 2 ** 30, 2),
                "realisations_per_chunk": cb,
                "kept_state": None}
         # trailing spans kept: their nonlinear-step inputs stored by the forward
