@@ -509,7 +509,14 @@ def main() -> int:
         plan.forward(field, seed=w.ase_seed, stream=stream)
     torch.cuda.synchronize()
 
-    sub_batches = 1  # the library's default: one stream per call
+    # the library's default (documented with ssfm_plan_set_forward_streams):
+    # each chunk as two concurrent parts when each part holds >= 2048 column
+    # tiles
+    sub_batches = 1
+    if info["path"] == 2:
+        chunk = info["chunk_realisations"] or batch
+        chunk = -(-batch // -(-batch // chunk))
+        sub_batches = 2 if chunk * info["n2"] // info["columns_per_tile"] >= 4096 else 1
     # ---- timed region: K calls as the library runs them ---------------------
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -589,11 +596,14 @@ def main() -> int:
                 torch.cuda.synchronize()
                 times.append(a0.elapsed_time(a1))
             ms = sorted(times)[len(times) // 2]  # median
-            # per-kernel breakdown of one more call (events around every launch)
+            # per-kernel breakdown of one more call (events around every
+            # launch; one stream, so that no two launches' windows overlap)
             if args.launch_events:
+                plan.set_forward_streams(1)
                 ssfm.ssfm_profile_begin(plan.handle)
                 plan.adjoint(field, grad, seed=w.ase_seed, stream=stream)
                 torch.cuda.synchronize()
+                plan.set_forward_streams(0)
                 for s_ in ssfm.ssfm_profile_end(plan.handle):
                     log(f"  adjoint call ({label}) {s_['name']}: {s_['launches']} launches, "
                         f"{s_['total_ms']:.1f} ms, "

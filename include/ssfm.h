@@ -136,8 +136,9 @@ int ssfm_plan_get_info(ssfm_plan_t plan, ssfm_plan_info* info);
  *   batch:  >= 1.  Realisation r of the batch draws its noise with key
  *           (seed, r * 2^16 + span).  On the four-step path a batch above
  *           the plan's chunk_realisations (ssfm_plan_info) runs as equal
- *           chunks through the whole link, one after the other, with the
- *           same bits as one pass over the batch.
+ *           chunks through the whole link, one after the other (each as
+ *           one or more concurrent parts, ssfm_plan_set_forward_streams),
+ *           with the same bits as one pass over the batch.
  *   stream: hipStream_t to order the work on (NULL = default stream).
  * Asynchronous with respect to the host: returns once the kernels are
  * enqueued; a fault inside a kernel surfaces at the caller's next
@@ -205,7 +206,9 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch,
  * working sets.  Without kept spans, the forward pass runs first over the
  * whole batch (in the forward's chunks), keeping every realisation's span
  * checkpoints, then the reverse sweep runs chunk by chunk; the bits are
- * those of one pass over the batch.  With a state budget each chunk's whole
+ * those of one pass over the batch; every chunk of either phase runs as
+ * one or more concurrent parts (ssfm_plan_set_forward_streams), each on its
+ * share of the chunk's workspace.  With a state budget each chunk's whole
  * adjoint runs on the workspace of one chunk, the budget applied per chunk
  * (so a chunk may keep more spans than a whole-batch pass would).
  * Workspace: four-step path n_spans * batch * n_pol * n_samples * 8 bytes
@@ -252,21 +255,25 @@ int ssfm_adjoint(ssfm_plan_t plan, const void* field_in, void* grad,
 int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad,
                          int64_t batch, uint64_t seed, void* stream);
 
-/* Concurrent sub-batches of a four-step call (n_samples >= 2^14):
- *   0 or 1  one stream (the default);
- *   2       ssfm_forward, ssfm_forward_spans and ssfm_adjoint split a batch
- *           of two or more realisations into two halves, one on the caller's
- *           stream and one on a worker stream of the device (created on
- *           first use, shared with ssfm_batch, default priority) forked from
- *           the caller's stream and joined back into it with events, so the
- *           call stays ordered on that stream.
- * Realisation b keeps its noise key and the halves run the same per-tile
- * arithmetic, so results are the same bit for bit either way.  Whether the
- * split is faster depends on the two streams reaching the GPU through
+/* Concurrent parts of a four-step call (n_samples >= 2^14).  ssfm_forward,
+ * ssfm_forward_spans and ssfm_adjoint run a large batch as sequential chunks
+ * (ssfm_plan_info.chunk_realisations); each chunk may run as consecutive
+ * parts of nearly equal size, the first on the caller's stream and the
+ * others on worker streams of the device (created on first use, shared with
+ * ssfm_batch, default priority) forked from the caller's stream and joined
+ * back into it with events, so the call stays ordered on that stream.  Parts
+ * on separate streams fill the tail of each pass with the other parts' work.
+ *   0      the library's choice (the default): two parts when each still
+ *          holds at least 2048 column tiles (batch * n2 / 8 >= 4096, e.g.
+ *          >= 128 realisations of 2^16 samples), else one;
+ *   1..5   that many parts (at most one per realisation).
+ * Realisation b keeps its noise key and every part runs the same per-tile
+ * arithmetic, so results are the same bit for bit whatever the setting.
+ * Whether parts are faster depends on the streams reaching the GPU through
  * different hardware queues, which the process's stream creation order
- * decides.  A split call does not use graph replay.  Not to be changed while
- * a call on the plan runs.  Errors: SSFM_EINVAL (NULL plan, streams outside
- * 0..2). */
+ * decides.  A call with two or more parts does not use graph replay.  Not to
+ * be changed while a call on the plan runs.  Errors: SSFM_EINVAL (NULL plan,
+ * streams outside 0..5). */
 int ssfm_plan_set_forward_streams(ssfm_plan_t plan, int32_t streams);
 
 /* Device memory, in bytes, that ssfm_adjoint may hold for the kept spans'

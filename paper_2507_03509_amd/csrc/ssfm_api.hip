@@ -161,8 +161,8 @@ struct ssfm_plan_s {
   uint64_t state_budget = 0;
   float2* adj_states = nullptr;
   size_t adj_states_bytes = 0;
-  // concurrent sub-batches of a four-step call: 0 or 1 (one stream, the
-  // default) or 2 (ssfm_plan_set_forward_streams)
+  // concurrent parts of a four-step call's chunks: 0 (the library's
+  // choice, forward_parts) or 1..5 (ssfm_plan_set_forward_streams)
   int forward_streams = 0;
   // working-set target of a four-step call's sequential chunks (bytes; 0:
   // the whole batch at once)
@@ -513,21 +513,6 @@ int run_forward(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed, uin
   return SSFM_OK;
 }
 
-// run_forward over the batch in the sequential chunks of chunk_batch (plain
-// forward calls: no checkpoints or stored states); realisation b keeps its
-// noise index real0 + b, so the bits are those of one whole-batch pass.
-int run_forward_chunked(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed,
-                        uint64_t real0, int s0, int s1, hipStream_t st) {
-  const int64_t cb = chunk_batch(p, batch, 1);
-  const size_t elems = (size_t)p->n_pol * p->n;
-  for (int64_t b0 = 0; b0 < batch; b0 += cb) {
-    const int64_t nb = std::min(cb, batch - b0);
-    const int rc = run_forward(p, field + (size_t)b0 * elems, nb, seed, real0 + (uint64_t)b0, s0,
-                               s1, st);
-    if (rc != SSFM_OK) return rc;
-  }
-  return SSFM_OK;
-}
 
 int check_call(ssfm_plan_t plan, const void* field, int64_t batch) {
   if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
@@ -846,42 +831,90 @@ BatchReplay& batch_replay() {
   return *r;
 }
 
-// Sub-batches a four-step call runs concurrently: one unless the plan asks
-// for two (ssfm_plan_set_forward_streams) and the batch has two realisations.
-// Two sub-batches on two streams can fill the tail of each pass and the gap
-// between dependent launches with the other sub-batch's work, when the two
-// streams reach the GPU through different hardware queues (which the streams'
-// creation order decides, not this library).
+// Parts a four-step chunk of `batch` realisations runs as concurrently: the
+// plan's setting (ssfm_plan_set_forward_streams), at most one per
+// realisation; by default two when each part still holds at least 2048
+// column tiles (four rounds of two workgroups on each of 256 CUs), else one.
+// Parts of a chunk on separate streams fill the tail of each pass (its last,
+// partly occupied round of workgroups) with the other parts' work, when the
+// streams reach the GPU through different hardware queues (which the
+// streams' creation order decides, not this library); together they keep
+// the chunk's working set.
+constexpr int64_t kPartTiles = 2048;
 int forward_parts(const ssfm_plan_s* p, int64_t batch) {
-  if (p->ks.path != 2 || batch < 2) return 1;
-  return p->forward_streams == 2 ? 2 : 1;
+  if (p->ks.path != 2) return 1;
+  int parts = p->forward_streams;
+  if (parts == 0) parts = batch * (p->ks.n2 / p->ks.wide.columns) >= 2 * kPartTiles ? 2 : 1;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(parts, batch));
 }
 
-// Run part(0, st) on the caller's stream and part(1, w) on a worker stream w
-// forked from st and joined back into it (also after an error, so that no
-// work is left unordered).
+// Run part(0, st) on the caller's stream and part(k, w_k), k = 1..parts-1,
+// on worker streams forked from st and joined back into it (also after an
+// error, so that no work is left unordered).
 template <typename F>
-int run_split(ssfm_plan_s* p, hipStream_t st, F&& part) {
+int run_split(ssfm_plan_s* p, hipStream_t st, int parts, F&& part) {
   hipStream_t ws[kBatchStreams];
   int rc = batch_streams(p->device, ws);
   if (rc != SSFM_OK) return rc;
-  hipEvent_t ev[2] = {};
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(ev[0], st);  // fork
-  if (e == hipSuccess) e = hipStreamWaitEvent(ws[0], ev[0], 0);
-  if (e != hipSuccess) {
-    for (hipEvent_t x : ev)
+  parts = std::min(parts, kBatchStreams + 1);
+  hipEvent_t fork = nullptr, join[kBatchStreams] = {};
+  auto destroy = [&] {
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipEvent_t x : join)
       if (x) (void)hipEventDestroy(x);
+  };
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (int k = 1; k < parts && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&join[k - 1], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(fork, st);
+  for (int k = 1; k < parts && e == hipSuccess; ++k) e = hipStreamWaitEvent(ws[k - 1], fork, 0);
+  if (e != hipSuccess) {
+    destroy();
     return api_fail_hip(e, "sub-batch fork");
   }
-  rc = part(1, ws[0]);
+  for (int k = parts - 1; k >= 1 && rc == SSFM_OK; --k) rc = part(k, ws[k - 1]);
   if (rc == SSFM_OK) rc = part(0, st);
-  hipError_t ej = hipEventRecord(ev[1], ws[0]);  // join
-  if (ej == hipSuccess) ej = hipStreamWaitEvent(st, ev[1], 0);
-  for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+  hipError_t ej = hipSuccess;
+  for (int k = 1; k < parts; ++k) {
+    hipError_t x = hipEventRecord(join[k - 1], ws[k - 1]);
+    if (x == hipSuccess) x = hipStreamWaitEvent(st, join[k - 1], 0);
+    if (ej == hipSuccess) ej = x;
+  }
+  destroy();
   if (rc != SSFM_OK) return rc;
   if (ej != hipSuccess) return api_fail_hip(ej, "sub-batch join");
+  return SSFM_OK;
+}
+
+// part(off, count, stream) over the realisations [0, nb) of a chunk: as one
+// part on st, or as forward_parts() consecutive parts of nearly equal size,
+// the first on st and the others on worker streams.
+template <typename F>
+int run_parts(ssfm_plan_s* p, int64_t nb, hipStream_t st, F&& part) {
+  const int parts = std::min(forward_parts(p, nb), kBatchStreams + 1);
+  if (parts < 2) return part(int64_t{0}, nb, st);
+  return run_split(p, st, parts, [&](int k, hipStream_t ws) {
+    const int64_t o0 = nb * k / parts, o1 = nb * (k + 1) / parts;
+    return part(o0, o1 - o0, ws);
+  });
+}
+
+// run_forward over the batch in the sequential chunks of chunk_batch (plain
+// forward calls: no checkpoints or stored states), each chunk as one or two
+// concurrent parts; realisation b keeps its noise index real0 + b, so the
+// bits are those of one whole-batch pass.
+int run_forward_chunked(ssfm_plan_s* p, float2* field, int64_t batch, uint64_t seed,
+                        uint64_t real0, int s0, int s1, hipStream_t st) {
+  const int64_t cb = chunk_batch(p, batch, 1);
+  const size_t elems = (size_t)p->n_pol * p->n;
+  for (int64_t b0 = 0; b0 < batch; b0 += cb) {
+    const int rc = run_parts(p, std::min(cb, batch - b0), st,
+                             [&](int64_t off, int64_t nb, hipStream_t ws) {
+                               return run_forward(p, field + (size_t)(b0 + off) * elems, nb, seed,
+                                                  real0 + (uint64_t)(b0 + off), s0, s1, ws);
+                             });
+    if (rc != SSFM_OK) return rc;
+  }
   return SSFM_OK;
 }
 
@@ -1063,19 +1096,19 @@ void adjoint_workspace(const ssfm_plan_s* plan, int64_t batch, size_t* work, siz
 // the previous adjoint call.
 int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int64_t batch,
                        uint64_t seed, hipStream_t st) {
-  // One stream: the batch in sequential chunks sized for two fields (state
-  // and cotangent).  Without kept spans the forward pass first runs over the
-  // whole batch in the forward's one-field chunks, keeping every
-  // realisation's span checkpoints, then the reverse sweep runs chunk by
-  // chunk; with kept spans each chunk's whole adjoint runs on the workspace
-  // of one chunk, the state budget applied per chunk.
-  const bool split = plan->ks.path == 2 && forward_parts(plan, batch) > 1;
-  const int64_t cb = split ? batch : chunk_batch(plan, batch, 2);
-  const int64_t fb = split ? batch : chunk_batch(plan, batch, 1);
+  // The batch in sequential chunks sized for two fields (state and
+  // cotangent), each chunk as one or two concurrent parts (run_parts, each
+  // part on its own share of the chunk's workspace).  Without kept spans the
+  // forward pass first runs over the whole batch in the forward's one-field
+  // chunks, keeping every realisation's span checkpoints, then the reverse
+  // sweep runs chunk by chunk; with kept spans each chunk's whole adjoint
+  // runs on the workspace of one chunk, the state budget applied per chunk.
+  const int64_t cb = chunk_batch(plan, batch, 2);
+  const int64_t fb = chunk_batch(plan, batch, 1);
   const size_t elems = (size_t)plan->n_pol * plan->n;
   const size_t slice = (size_t)cb * elems;
   const size_t span_state_bytes = (size_t)plan->steps * slice * sizeof(float2);
-  const bool two_phase = plan->ks.path == 2 && !split && cb < batch &&
+  const bool two_phase = plan->ks.path == 2 && cb < batch &&
                          plan->state_budget < span_state_bytes;
   size_t work_elems, ckpt_elems;
   adjoint_workspace(plan, cb, &work_elems, &ckpt_elems);
@@ -1108,18 +1141,29 @@ int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int6
     return run_adjoint_lds(plan, field_in, grad, batch, seed, st, plan->adj_ckpt, plan->adj_work);
   if (two_phase) {
     const size_t stride = (size_t)batch * elems;  // between spans' checkpoints
+    // a part at offset off of a chunk: its realisations' slice of the work
+    // buffer (one field in the forward pass, state and cotangent in the
+    // reverse sweep) and of every span's checkpoints
     for (int64_t b0 = 0; b0 < batch; b0 += fb) {
-      const size_t o = (size_t)b0 * elems;
-      const int rc = adjoint_forward(plan, static_cast<const float2*>(field_in) + o,
-                                     std::min(fb, batch - b0), seed, (uint64_t)b0, st,
-                                     plan->adj_work, plan->adj_ckpt + o, stride, nullptr, 0);
+      const int rc = run_parts(plan, std::min(fb, batch - b0), st,
+                               [&](int64_t off, int64_t nb, hipStream_t ws) {
+                                 const size_t o = (size_t)(b0 + off) * elems;
+                                 return adjoint_forward(
+                                     plan, static_cast<const float2*>(field_in) + o, nb, seed,
+                                     (uint64_t)(b0 + off), ws, plan->adj_work + (size_t)off * elems,
+                                     plan->adj_ckpt + o, stride, nullptr, 0);
+                               });
       if (rc != SSFM_OK) return rc;
     }
     for (int64_t b0 = 0; b0 < batch; b0 += cb) {
-      const size_t o = (size_t)b0 * elems;
-      const int rc = adjoint_reverse(plan, static_cast<float2*>(grad) + o,
-                                     std::min(cb, batch - b0), st, plan->adj_work,
-                                     plan->adj_ckpt + o, stride, nullptr, 0);
+      const int rc = run_parts(plan, std::min(cb, batch - b0), st,
+                               [&](int64_t off, int64_t nb, hipStream_t ws) {
+                                 const size_t o = (size_t)(b0 + off) * elems;
+                                 return adjoint_reverse(
+                                     plan, static_cast<float2*>(grad) + o, nb, ws,
+                                     plan->adj_work + 2 * (size_t)off * elems, plan->adj_ckpt + o,
+                                     stride, nullptr, 0);
+                               });
       if (rc != SSFM_OK) return rc;
     }
     return SSFM_OK;
@@ -1146,30 +1190,22 @@ int adjoint_serialised(ssfm_plan_s* plan, const void* field_in, void* grad, int6
     }
     if (kept > 0) plan->adj_states_bytes = (size_t)kept * span_state_bytes;
   }
-  // two concurrent sub-batches (when the plan asks for them) on carved
-  // halves of the workspace, else the chunks one after the other
-  if (!split) {
-    for (int64_t b0 = 0; b0 < batch; b0 += cb) {
-      const size_t o = (size_t)b0 * elems;
-      const int rc = run_adjoint(plan, static_cast<const float2*>(field_in) + o,
-                                 static_cast<float2*>(grad) + o, std::min(cb, batch - b0), seed,
-                                 (uint64_t)b0, st, plan->adj_work, plan->adj_ckpt,
-                                 plan->adj_states, kept);
-      if (rc != SSFM_OK) return rc;
-    }
-    return SSFM_OK;
+  // the chunks one after the other, a part at offset off of a chunk on its
+  // realisations' share of the chunk's work, checkpoints and stored states
+  for (int64_t b0 = 0; b0 < batch; b0 += cb) {
+    const int rc = run_parts(
+        plan, std::min(cb, batch - b0), st, [&](int64_t off, int64_t nb, hipStream_t ws) {
+          const size_t o = (size_t)(b0 + off) * elems, oc = (size_t)off * elems;
+          return run_adjoint(plan, static_cast<const float2*>(field_in) + o,
+                             static_cast<float2*>(grad) + o, nb, seed, (uint64_t)(b0 + off), ws,
+                             plan->adj_work + 2 * oc, plan->adj_ckpt + (size_t)plan->spans * oc,
+                             plan->adj_states ? plan->adj_states + (size_t)kept * plan->steps * oc
+                                              : nullptr,
+                             kept);
+        });
+    if (rc != SSFM_OK) return rc;
   }
-  const int64_t b0 = batch / 2;
-  const int64_t sub[2] = {b0, batch - b0};
-  const int64_t off[2] = {0, b0};
-  return run_split(plan, st, [&](int h, hipStream_t ws) {
-    const size_t o = (size_t)off[h] * elems;
-    return run_adjoint(plan, static_cast<const float2*>(field_in) + o, static_cast<float2*>(grad) + o,
-                       sub[h], seed, (uint64_t)off[h], ws, plan->adj_work + 2 * o,
-                       plan->adj_ckpt + (size_t)plan->spans * o,
-                       plan->adj_states ? plan->adj_states + (size_t)kept * plan->steps * o : nullptr,
-                       kept);
-  });
+  return SSFM_OK;
 }
 
 
@@ -1257,19 +1293,9 @@ int ssfm_forward_spans(ssfm_plan_t plan, void* field, int64_t batch, uint64_t se
   DeviceGuard guard(plan->device);
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (forward_parts(plan, batch) > 1) {
-    // two sub-batches, on the caller's stream and a worker stream (no graph
-    // replay: the two streams' launches interleave)
-    const int64_t b0 = batch / 2;
-    float2* f = static_cast<float2*>(field);
-    const size_t o = (size_t)b0 * plan->n_pol * plan->n;
-    return run_split(plan, st, [&](int h, hipStream_t ws) {
-      return h == 0 ? run_forward(plan, f, b0, seed, realization0, span_begin, span_end, ws)
-                    : run_forward(plan, f + o, batch - b0, seed, realization0 + (uint64_t)b0,
-                                  span_begin, span_end, ws);
-    });
-  }
-  if (!use_graphs(plan))
+  // two concurrent parts per chunk: no graph replay (the two streams'
+  // launches interleave)
+  if (forward_parts(plan, batch) > 1 || !use_graphs(plan))
     return run_forward_chunked(plan, static_cast<float2*>(field), batch, seed, realization0,
                                span_begin, span_end, st);
   // A call repeating the previous one (same buffer, batch, seed, spans and
@@ -1447,8 +1473,9 @@ int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad, int
 int ssfm_plan_set_forward_streams(ssfm_plan_t plan, int32_t streams) {
   ssfm::api_clear_error();
   if (!plan) return api_fail(SSFM_EINVAL, "plan is NULL");
-  if (streams < 0 || streams > 2)
-    return api_fail(SSFM_EINVAL, "streams must be 0 (default), 1 or 2, got %d", streams);
+  if (streams < 0 || streams > kBatchStreams + 1)
+    return api_fail(SSFM_EINVAL, "streams must be 0 (default) .. %d, got %d", kBatchStreams + 1,
+                    streams);
   plan->forward_streams = streams;
   return SSFM_OK;
 }
@@ -1600,8 +1627,11 @@ int ssfm_plan_autotune(ssfm_plan_t plan, int64_t batch, void* stream, ssfm_tune_
   DeviceGuard guard(plan->device);
   if (guard.status != hipSuccess) return api_fail_hip(guard.status, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // a forward call runs larger batches in chunks: tune the chunk's shape
-  batch = chunk_batch(plan, batch, 1);
+  // a forward call runs larger batches in chunks, each as one or more
+  // concurrent parts: tune the shape of the largest part
+  const int64_t chunk = chunk_batch(plan, batch, 1);
+  const int parts = forward_parts(plan, chunk);
+  batch = (chunk + parts - 1) / parts;
   const size_t bytes = (size_t)batch * plan->n_pol * plan->n * sizeof(float2);
   float2* f = nullptr;
   if (hipMalloc(&f, bytes) != hipSuccess)
@@ -1670,8 +1700,10 @@ int ssfm_plan_autotune(ssfm_plan_t plan, int64_t batch, void* stream, ssfm_tune_
   sh.wide_cols = (best_idx >> 1) != 0;
   sh.wide_rows = (best_idx & 1) != 0;
   {
+    // both part sizes of the chunk (they differ by at most one)
     std::lock_guard<std::mutex> lock(plan->tune_mu);
     plan->tuned[batch] = sh;
+    plan->tuned[chunk / parts] = sh;
   }
   {
     // the replay graph may hold the previous shape

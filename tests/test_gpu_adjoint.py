@@ -233,10 +233,11 @@ def test_adjoint_state_budget_reuse_and_release(ssfm):
         plan.close()
 
 
-@pytest.mark.parametrize("kept", [0, 1])
-def test_adjoint_two_stream_split_is_bitwise(ssfm, kept):
-    # the adjoint of two concurrent sub-batches (on carved halves of the
-    # workspace) against the single-stream call: the same bits
+@pytest.mark.parametrize("kept,parts", [(0, 2), (1, 2), (0, 3)])
+def test_adjoint_two_stream_split_is_bitwise(ssfm, kept, parts):
+    # the adjoint of concurrent parts (each on its share of the workspace)
+    # against the single-stream call: the same bits
+    print(f"case kept={kept} parts={parts}", flush=True)
     n, steps, b = 1 << 15, 3, 5
     ln = link(2, n, spans=2, steps=steps)
     rng = np.random.default_rng(77 + kept)
@@ -248,12 +249,12 @@ def test_adjoint_two_stream_split_is_bitwise(ssfm, kept):
     try:
         plan.set_state_memory(kept * steps * b * 2 * n * 8)
         out = {}
-        for streams in (2, 1):
+        for streams in (parts, 1):
             plan.set_forward_streams(streams)
             out[streams] = plan.adjoint(xt, gt.clone(), seed=6)
         torch.cuda.synchronize()
-        assert torch.equal(out[1], out[2])
-        got = out[2].cpu().numpy().astype(np.complex128)
+        assert torch.equal(out[1], out[parts])
+        got = out[parts].cpu().numpy().astype(np.complex128)
     finally:
         plan.close()
     for r in (0, b - 1):

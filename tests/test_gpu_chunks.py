@@ -1,6 +1,7 @@
-"""Batches above the plan's chunk size run as sequential chunks: the forward
-call (direct and graph replay) and the adjoint give the bits of one pass over
-the whole batch, and the oracle's result.  SSFM_CHUNK_MIB, read when a plan
+"""Batches above the plan's chunk size run as sequential chunks, each as one
+or more concurrent parts: the forward call (direct and graph replay) and the
+adjoint give the bits of one pass over the whole batch, and the oracle's
+result.  SSFM_CHUNK_MIB, read when a plan
 is built, sets the chunk size (0: none), so small fields exercise several
 chunks, including a shorter last one."""
 
@@ -41,9 +42,12 @@ def plan_with_chunks(ssfm, monkeypatch, ln, mib):
 # (n, n_pol, batch): 2^14 dual-pol is 256 KiB per realisation, so 1 MiB
 # chunks hold 4 realisations (the adjoint's, two fields each, 2); 2^16
 # single-pol is 512 KiB (chunks of 2 and 1)
-@pytest.mark.parametrize("n,n_pol,batch", [(1 << 14, 2, 7), (1 << 16, 1, 5)])
-def test_chunked_calls_equal_one_pass(ssfm, monkeypatch, n, n_pol, batch):
-    print(f"case n={n} n_pol={n_pol} batch={batch}", flush=True)
+# parts: each chunk of the chunked plan as that many concurrent parts (the
+# one-pass plan runs on one stream)
+@pytest.mark.parametrize("n,n_pol,batch,parts", [(1 << 14, 2, 7, 1), (1 << 16, 1, 5, 1),
+                                                 (1 << 14, 2, 7, 2), (1 << 16, 1, 5, 2)])
+def test_chunked_calls_equal_one_pass(ssfm, monkeypatch, n, n_pol, batch, parts):
+    print(f"case n={n} n_pol={n_pol} batch={batch} parts={parts}", flush=True)
     ln = link(n_pol, n)
     rng = np.random.default_rng(n + batch)
     x = np.stack([dual_pol_field(rng, n_pol, n, 2, 64e9, 0.1, 4.0) for _ in range(batch)])
@@ -52,6 +56,8 @@ def test_chunked_calls_equal_one_pass(ssfm, monkeypatch, n, n_pol, batch):
     g = g.astype(np.complex64)
     whole = plan_with_chunks(ssfm, monkeypatch, ln, 0)
     chunked = plan_with_chunks(ssfm, monkeypatch, ln, 1)
+    whole.set_forward_streams(1)
+    chunked.set_forward_streams(parts)
     try:
         assert whole.info["chunk_realisations"] == 0
         per = n_pol * n * 8

@@ -268,22 +268,24 @@ def test_large_nonlinear_phase(ssfm, n, n_pol):
 
 
 # ---------------------------------------------------------------------------
-# two concurrent sub-batches (ssfm_plan_set_forward_streams(plan, 2)): the
-# halves run on the caller's stream and a worker stream; the single-stream
-# call gives the same bits (same per-tile arithmetic, realisation b keeps its
-# noise key)
+# concurrent parts (ssfm_plan_set_forward_streams(plan, k)): the parts run on
+# the caller's stream and worker streams; the single-stream call gives the
+# same bits (same per-tile arithmetic, realisation b keeps its noise key)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,batch", [(1 << 16, 128), (1 << 16, 129), (1 << 14, 3)])
-def test_two_stream_split_is_bitwise(ssfm, n, batch):
-    print(f"case n={n} batch={batch}", flush=True)
+@pytest.mark.parametrize("n,batch,parts", [(1 << 16, 128, 2), (1 << 16, 129, 2), (1 << 14, 3, 2),
+                                           (1 << 14, 7, 3), (1 << 14, 9, 5), (1 << 16, 130, 0)])
+def test_two_stream_split_is_bitwise(ssfm, n, batch, parts):
+    # parts = 0: the library's own choice (two parts at >= 128 realisations
+    # of 2^16 samples)
+    print(f"case n={n} batch={batch} parts={parts}", flush=True)
     ln = link(2, n, spans=2, steps=3)
     a0 = qam(2, n, seed=batch, batch=2)
     x = np.concatenate([a0] * ((batch + 1) // 2))[:batch]
     t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).cuda()
     plan = ssfm.Plan(ln)
     try:
-        plan.set_forward_streams(2)
+        plan.set_forward_streams(parts)
         split = t.clone()
         plan.forward(split, seed=4)
         plan.set_forward_streams(1)
