@@ -199,11 +199,27 @@ __global__ __launch_bounds__(P * C * (N1 / 16)) __attribute__((amdgpu_waves_per_
       float2* nbuf = reinterpret_cast<float2*>(lds3_raw) + p * (N1 * C) + c;
       if (noisy) {
         __syncthreads();  // the inverse FFT's LDS reads are done
+        if constexpr (PAIR) {
+          // one draw of a time sample gives both polarisations' noise: the
+          // lane pair splits the rows, lane p drawing rows j + T (8 p + r)
+          // for both, then each reads its own polarisation's 16 values
+          float2* nb0 = reinterpret_cast<float2*>(lds3_raw) + c;
 #pragma unroll 1
-        for (int r = 0; r < 16; ++r) {
-          const uint64_t t = (uint64_t)(j + T * r) * (uint64_t)a.n2 + (uint64_t)n2;
-          const u64x4 w = philox4x64_10(t, 0, 0, 0, key0, key1);
-          nbuf[(j + T * r) * C] = p == 0 ? box_muller(w.w[0], w.w[1]) : box_muller(w.w[2], w.w[3]);
+          for (int r = 8 * p; r < 8 * p + 8; ++r) {
+            const int row = j + T * r;
+            const uint64_t t = (uint64_t)row * (uint64_t)a.n2 + (uint64_t)n2;
+            const u64x4 w = philox4x64_10(t, 0, 0, 0, key0, key1);
+            nb0[row * C] = box_muller(w.w[0], w.w[1]);
+            nb0[N1 * C + row * C] = box_muller(w.w[2], w.w[3]);
+          }
+          wave_sync();  // the pair lanes are in one wave
+        } else {
+#pragma unroll 1
+          for (int r = 0; r < 16; ++r) {
+            const uint64_t t = (uint64_t)(j + T * r) * (uint64_t)a.n2 + (uint64_t)n2;
+            const u64x4 w = philox4x64_10(t, 0, 0, 0, key0, key1);
+            nbuf[(j + T * r) * C] = p == 0 ? box_muller(w.w[0], w.w[1]) : box_muller(w.w[2], w.w[3]);
+          }
         }
       }
 #pragma unroll
