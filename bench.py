@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--dft16", action="store_true",
                     help="time the radix-16 DFT stage prototype: the FFTs' vector "
                          "butterfly against the matrix-core product (one JSON line)")
+    ap.add_argument("--orchestration", action="store_true",
+                    help="time the ordering points of a split-step call: a dependent "
+                         "kernel boundary (graph replay, direct) against a device-wide "
+                         "barrier in one cooperative kernel (one JSON line)")
     ap.add_argument("--launch-events", type=int, default=1,
                     help="time every launch with HIP events for the roofline and the "
                          "kernel breakdowns (0: skip them, e.g. under counter collection)")
@@ -196,6 +200,43 @@ def bench_dft16(args) -> int:
         "methods": res,
         "mfma_over_valu_time": res["valu_butterfly"]["transforms_per_s"] /
                                res["mfma_f64_matrix"]["transforms_per_s"],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_orchestration(args) -> int:
+    """GPU time per ordering point between dependent passes, by workgroup
+    count: a boundary between dependent launches of an empty kernel, replayed
+    from a graph (method 0) or launched directly (1), against a device-wide
+    barrier crossed by every workgroup of one cooperative kernel (2) -- the
+    persistent alternative to graph replay for the four-step path, which
+    needs two such points per split step."""
+    import torch
+
+    import paper_2507_03509_amd as ssfm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    ssfm.load_library()
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
+    rounds = 2000
+    res = {}
+    for name, method in (("graph_replay", 0), ("direct_launch", 1), ("grid_barrier", 2)):
+        res[name] = {}
+        for wg in (8, 32, 64, 128, 256, 512):
+            ssfm.ssfm_orchestration_probe(method, wg, 100, stream)  # warm-up
+            us = min(ssfm.ssfm_orchestration_probe(method, wg, rounds, stream)
+                     for _ in range(max(1, args.steps)))
+            res[name][str(wg)] = round(us, 3)
+            log(f"{name}, {wg} workgroups: {us:.3f} us per ordering point")
+    out = {
+        "metric": "GPU time per ordering point between dependent passes", "unit": "us",
+        "value": res["graph_replay"]["512"], "higher_is_better": False,
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "dtype": "none",
+        "data": "synthetic", "config": {"workload": f"{rounds} ordering points, 256-lane workgroups"},
+        "us_per_point": res,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -435,6 +476,8 @@ def main() -> int:
     args = parse()
     if args.dft16 and args.gpus == 1:
         return bench_dft16(args)
+    if args.orchestration and args.gpus == 1:
+        return bench_orchestration(args)
     if args.workload == 4 and args.gpus == 1:
         return bench_mixed_batch(args)
     if args.workload == 5 and args.gpus == 1:

@@ -373,6 +373,23 @@ int ssfm_stream_copy(void* dst, const void* src, int64_t bytes, void* stream);
  * [0, 2^20]), SSFM_EHIP. */
 int ssfm_dft16_rounds(int method, void* data, int64_t count, int rounds, void* stream);
 
+/* Measurement utility (not part of the propagation): the cost of one
+ * ordering point between dependent passes of a split-step call, as the
+ * four-step path could order them.  method 0: a captured graph of `rounds`
+ * dependent launches of an empty kernel of `workgroups` workgroups (256
+ * lanes), replayed (how repeated calls run); 1: the same launches issued
+ * directly on `stream`; 2: one cooperative kernel of `workgroups` resident
+ * workgroups crossing `rounds` device-wide barriers (an atomic arrival
+ * counter and generation word, bounded polling) -- the persistent
+ * alternative.  *us_per_round receives the GPU time per launch or barrier
+ * (HIP events on `stream`).  Synchronous: waits for the work.  Errors:
+ * SSFM_EINVAL (NULL us_per_round, method not 0..2, rounds outside
+ * [1, 65536], workgroups outside [1, 65536], or for method 2 above the
+ * device's resident capacity), SSFM_ENOMEM, SSFM_EHIP (including a barrier
+ * wait that ran out). */
+int ssfm_orchestration_probe(int method, int32_t workgroups, int32_t rounds, void* stream,
+                             double* us_per_round);
+
 /* Static description of a status code (never NULL). */
 const char* ssfm_status_string(int status);
 

@@ -24,6 +24,7 @@ __all__ = [
     "ssfm_batch", "ssfm_status_string", "ssfm_last_error", "ssfm_version", "Plan",
     "ssfm_profile_begin", "ssfm_profile_end", "SsfmKernelStats", "propagate",
     "SsfmTuneInfo", "ssfm_plan_autotune", "ssfm_stream_copy", "ssfm_dft16_rounds",
+    "ssfm_orchestration_probe",
     "ssfm_plan_set_state_memory", "ssfm_plan_set_forward_streams",
     "SSFM_OK", "SSFM_EINVAL", "SSFM_ENOMEM", "SSFM_EHIP", "SSFM_EUNSUPPORTED",
     "SSFM_FLAG_FP32_ARITHMETIC",
@@ -147,6 +148,8 @@ def load_library() -> ctypes.CDLL:
     lib.ssfm_plan_autotune.argtypes = [P, I64, VP, ctypes.POINTER(SsfmTuneInfo)]
     lib.ssfm_stream_copy.argtypes = [VP, VP, I64, VP]
     lib.ssfm_dft16_rounds.argtypes = [ctypes.c_int, VP, I64, ctypes.c_int, VP]
+    lib.ssfm_orchestration_probe.argtypes = [ctypes.c_int, I32, I32, VP,
+                                             ctypes.POINTER(ctypes.c_double)]
     lib.ssfm_profile_begin.argtypes = [P]
     lib.ssfm_profile_end.argtypes = [P, ctypes.POINTER(SsfmKernelStats), ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_int)]
@@ -159,7 +162,8 @@ def load_library() -> ctypes.CDLL:
                  "ssfm_forward_spans", "ssfm_adjoint", "ssfm_batch", "ssfm_version",
                  "ssfm_profile_begin", "ssfm_profile_end", "ssfm_plan_autotune",
                  "ssfm_stream_copy", "ssfm_dft16_rounds", "ssfm_plan_set_state_memory",
-                 "ssfm_plan_set_forward_streams", "ssfm_adjoint_noalloc", "ssfm_dft"):
+                 "ssfm_plan_set_forward_streams", "ssfm_adjoint_noalloc", "ssfm_dft",
+                 "ssfm_orchestration_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -360,6 +364,18 @@ def ssfm_stream_copy(dst, src, stream=None) -> None:
         raise ValueError("dst and src differ in size")
     _check(load_library().ssfm_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes,
                                            _stream_ptr(src, stream)), "ssfm_stream_copy")
+
+
+def ssfm_orchestration_probe(method: int, workgroups: int, rounds: int, stream=None) -> float:
+    """GPU microseconds per ordering point: 0 graph-replayed dependent
+    launches, 1 direct launches, 2 device-wide barriers in one cooperative
+    kernel (see include/ssfm.h)."""
+    us = ctypes.c_double(0.0)
+    st = stream.cuda_stream if stream is not None else None
+    _check(load_library().ssfm_orchestration_probe(int(method), int(workgroups), int(rounds), st,
+                                                   ctypes.byref(us)),
+           "ssfm_orchestration_probe")
+    return us.value
 
 
 def ssfm_dft16_rounds(method: int, data, rounds: int, stream=None) -> None:
