@@ -271,8 +271,9 @@ int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad,
  * arithmetic, so results are the same bit for bit whatever the setting.
  * Whether parts are faster depends on the streams reaching the GPU through
  * different hardware queues, which the process's stream creation order
- * decides.  A call with two or more parts does not use graph replay.  Not to
- * be changed while a call on the plan runs.  Errors: SSFM_EINVAL (NULL plan,
+ * decides.  A call with two or more parts does not use graph replay.
+ * SSFM_FORWARD_STREAMS (0..5) in the environment at plan creation sets a
+ * plan's initial setting.  Not to be changed while a call on the plan runs.  Errors: SSFM_EINVAL (NULL plan,
  * streams outside 0..5). */
 int ssfm_plan_set_forward_streams(ssfm_plan_t plan, int32_t streams);
 

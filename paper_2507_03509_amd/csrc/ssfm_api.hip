@@ -1244,6 +1244,12 @@ int ssfm_plan(const ssfm_link* link, int hip_device, ssfm_plan_t* out) {
     const char* env = getenv("SSFM_CHUNK_MIB");
     p->chunk_bytes = (size_t)(env ? std::max(0, atoi(env)) : 256) << 20;
   }
+  // concurrent parts per chunk: SSFM_FORWARD_STREAMS (0..5) sets the plan's
+  // initial setting, as ssfm_plan_set_forward_streams would
+  {
+    const char* env = getenv("SSFM_FORWARD_STREAMS");
+    if (env) p->forward_streams = std::min(std::max(0, atoi(env)), kBatchStreams + 1);
+  }
   if (!ssfm::select_kernels(p->n, p->n_pol, (link->flags & SSFM_FLAG_FP32_ARITHMETIC) != 0, p->ks)) {
     delete p;
     return api_fail(SSFM_EUNSUPPORTED, "no kernel for n_samples = %lld", (long long)link->n_samples);
