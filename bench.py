@@ -413,6 +413,25 @@ def bench_ldbp(args) -> int:
     # LDBP_FWD_STEPS steps per launch, so a call is ceil(K / that) equal launches
     ms_fwd_kernel = timed(lambda: model.forward(x, taps, xi), reps)
     fwd_launches = -(-K // LDBP_FWD_STEPS)
+    # the backward call alone (its cotangent, overwritten by each call, is
+    # restored from a copy first: one 2 x 2^14 x 64 complex64 copy per call)
+    zb = model.forward(x, taps, xi, ck)
+    _, gb = model.loss(zb, sym, mfd, want_grad=True)
+    gw = gb.clone()
+
+    def bwd():
+        gw.copy_(gb)
+        model.backward(x, zb, taps, xi, ck, gw)
+
+    ms_bwd = timed(bwd, reps)
+    # algorithmic FP64 flops of the backward per span and sample: the span's
+    # inner states recomputed (S - 1 forward steps) and S reverse steps of FIR
+    # transpose (8 T P), tap gradient (8 T P) and Kerr pullback (~25 P)
+    S = cfg.steps_per_span
+    fwd_step_flops = P * 8 * cfg.n_taps + 9 * P + 1
+    rev_step_flops = 2 * P * 8 * cfg.n_taps + 25 * P
+    bwd_flops = B * N * (K // S) * ((S - 1) * fwd_step_flops + S * rev_step_flops)
+    bwd_tflops = bwd_flops / (ms_bwd * 1e-3) / 1e12
     work = B * N * K                                   # sample-steps per pass
     # algorithmic FP64 flops per sample-step: FIR 8 T per polarisation
     # (T complex multiply-adds), Kerr 3 P (|y|^2) + 1 (phase) + 6 P (rotation);
@@ -423,7 +442,8 @@ def bench_ldbp(args) -> int:
     value = work / (ms_train / 1e3)
     log(f"LDBP {B} x {P} x 2^{int(math.log2(N))}, K={K}: forward+loss {ms_fwd:.3f} ms, "
         f"train step {ms_train:.3f} ms ({ms_train / ms_fwd:.2f}x), forward kernel "
-        f"{ms_fwd_kernel:.3f} ms = {achieved:.1f} TFLOP/s FP64, loss {float(state['loss'][0]):.4e}")
+        f"{ms_fwd_kernel:.3f} ms = {achieved:.1f} TFLOP/s FP64, backward call {ms_bwd:.3f} ms = "
+        f"{bwd_tflops:.1f} TFLOP/s FP64, loss {float(state['loss'][0]):.4e}")
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -458,6 +478,10 @@ def bench_ldbp(args) -> int:
                    "sample_steps_per_pass": work, "parallelism": "single-gpu"},
         "ms_forward_and_loss": round(ms_fwd, 4), "ms_train_step": round(ms_train, 4),
         "fwd_adjoint_over_fwd": round(ms_train / ms_fwd, 3),
+        "backward": {"ms_per_call": round(ms_bwd, 4), "achieved_tflops": round(bwd_tflops, 2),
+                     "frac": round(bwd_tflops / 78.6, 4),
+                     "algorithmic_flops_per_call": bwd_flops,
+                     "note": "includes one cotangent copy per call"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                      "kernel": "ldbp_fwd",

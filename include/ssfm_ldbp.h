@@ -38,7 +38,15 @@
  * asynchronous on `stream` (NULL = default stream) and returns a status
  * code from ssfm.h; ssfm_last_error() describes a failure.  A handle owns
  * device workspace that it grows on first use: calls on one handle must not
- * run concurrently (serialise them on one stream).
+ * run concurrently (serialise them on one stream).  ssfm_ldbp_backward runs
+ * the two halves of a batch concurrently, one on `stream` and one on a
+ * worker stream of the handle (created on first use, default priority)
+ * forked from `stream` and joined back into it, when each half still fills
+ * 512 workgroups per launch; the results are the same bits either way.
+ * SSFM_LDBP_STREAMS in the environment at handle creation sets 1 (one
+ * stream) or 2..4 (that many parts, on as many streams, in
+ * ssfm_ldbp_forward and ssfm_ldbp_backward whenever the batch has as many
+ * realisations).
  */
 #ifndef SSFM_LDBP_H_
 #define SSFM_LDBP_H_

@@ -30,7 +30,7 @@ constexpr int kBwdRegion = 1024;
 constexpr int kFwdMaxRegion = 512 * L::R;  // forward workgroup <= 512 lanes
 constexpr int kBwdMaxRegion = 256 * L::R;  // backward workgroup <= 256 lanes
 constexpr int kLossSymbols = 256;          // symbols per loss workgroup
-constexpr int kMfSamples = 512;            // samples per matched-filter-adjoint workgroup
+constexpr int kMfSamples = 1024;           // samples per matched-filter-adjoint workgroup
 
 int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
@@ -90,6 +90,13 @@ struct ssfm_ldbp_s {
   ssfm_ldbp_desc d{};
   int device = 0;
   int fwd_tile = kFwdTile, fwd_steps = kFwdSteps, bwd_region = kBwdRegion;
+  // parts of a call's batch run concurrently on the caller's stream and
+  // the workers (forked and joined with the events): 0 two in the backward
+  // by its launch size (run_halves), 1 none, 2..4 that many parts in the
+  // forward and the backward; SSFM_LDBP_STREAMS
+  int streams = 0;
+  hipStream_t worker[3] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[3] = {};
   // workspace: padded taps [K][15], then a region sized for the largest call
   cd* taps15 = nullptr;
   unsigned char* ws = nullptr;
@@ -141,6 +148,52 @@ int ensure_ws(ssfm_ldbp_s* h, size_t bytes, hipStream_t st) {
   return SSFM_OK;
 }
 
+// part(b0, count, stream) over the realisations [0, batch) of a call: as one
+// part on st, or as two halves, [0, batch/2) on st and the rest on the
+// handle's worker stream, forked from st and joined back into it (also after
+// an error, so no work is left unordered).  A launch of `blocks` workgroups
+// per realisation ends in a partly filled round of workgroups; the other
+// half's launches fill it.  by_size: the halves run by default when each
+// still has 512 or more workgroups per launch (the backward: 1088
+// workgroups at two per CU, 2.1 rounds per launch; at 64 x 2 x 2^14 the
+// training step went from 1.00 to 0.87 ms), else only when the handle asks
+// (the forward: 1024 workgroups at three per CU measured 13 % slower as
+// halves; three or four parts were no faster than two).  The setting is the
+// number of parts (1..4) when the handle asks.  Every workgroup computes
+// what it computes in one launch over the batch, so the results are the
+// same bits.
+template <typename F>
+int run_halves(ssfm_ldbp_s* h, int64_t batch, int64_t blocks, bool by_size, hipStream_t st,
+               F&& part) {
+  int parts = h->streams >= 2 ? h->streams : (h->streams == 0 && by_size && batch * blocks >= 1024) ? 2 : 1;
+  parts = (int)std::min<int64_t>(parts, batch);
+  if (parts < 2) return part(int64_t{0}, batch, st);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < parts - 1 && e == hipSuccess; ++k) {
+    if (!h->worker[k]) e = hipStreamCreateWithFlags(&h->worker[k], hipStreamNonBlocking);
+    if (e == hipSuccess && !h->join_ev[k])
+      e = hipEventCreateWithFlags(&h->join_ev[k], hipEventDisableTiming);
+  }
+  if (e == hipSuccess && !h->fork_ev) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(h->fork_ev, st);
+  for (int k = 0; k < parts - 1 && e == hipSuccess; ++k) e = hipStreamWaitEvent(h->worker[k], h->fork_ev, 0);
+  if (e != hipSuccess) return api_fail_hip(e, "ldbp: fork onto the worker streams");
+  int rc = SSFM_OK;
+  for (int k = parts - 1; k >= 0 && rc == SSFM_OK; --k) {
+    const int64_t o0 = batch * k / parts, o1 = batch * (k + 1) / parts;
+    rc = part(o0, o1 - o0, k == 0 ? st : h->worker[k - 1]);
+  }
+  hipError_t ej = hipSuccess;
+  for (int k = 0; k < parts - 1; ++k) {
+    hipError_t x = hipEventRecord(h->join_ev[k], h->worker[k]);
+    if (x == hipSuccess) x = hipStreamWaitEvent(st, h->join_ev[k], 0);
+    if (ej == hipSuccess) ej = x;
+  }
+  if (rc != SSFM_OK) return rc;
+  if (ej != hipSuccess) return api_fail_hip(ej, "ldbp: join the worker streams");
+  return SSFM_OK;
+}
+
 // The dynamic-LDS limit is a property of the kernel (process-wide): only
 // ever raise it, so that no handle lowers it below another's need.
 std::mutex g_lds_mutex;
@@ -172,10 +225,12 @@ int check_ptr(const void* p, const char* what) {
   return SSFM_OK;
 }
 
-// Forward over all steps: src -> dst with checkpoints (or temporary
-// ping-pong states in tmp when ckpt is NULL and more than one launch runs).
+// Forward over all steps of the realisations [b0, b0 + count) of a call of
+// `batch`: src -> dst with checkpoints (or temporary ping-pong states in tmp
+// when ckpt is NULL and more than one launch runs); every array holds the
+// whole call's batch.
 int run_forward(ssfm_ldbp_s* h, const float2* src, float2* dst, const double* xi, int64_t batch,
-                float2* ckpt, float2* tmp, hipStream_t st) {
+                int64_t b0, int64_t count, float2* ckpt, float2* tmp, hipStream_t st) {
   const int K = h->d.n_steps, S = h->d.steps_per_span;
   const int chunk = h->fwd_chunk();
   const int64_t elems = h->field_elems(batch);
@@ -196,6 +251,8 @@ int run_forward(ssfm_ldbp_s* h, const float2* src, float2* dst, const double* xi
     a.xi = xi;
     a.n = h->d.n_samples;
     a.batch = batch;
+    a.b0 = b0;
+    a.count = count;
     a.k0 = k0;
     a.k1 = k1;
     a.spans_steps = S;
@@ -310,6 +367,7 @@ int ssfm_ldbp_create(const ssfm_ldbp_desc* desc, int hip_device, ssfm_ldbp_t* ou
   h->fwd_tile = env_int("SSFM_LDBP_FWD_TILE", kFwdTile);
   h->fwd_steps = env_int("SSFM_LDBP_FWD_STEPS", kFwdSteps);
   h->bwd_region = env_int("SSFM_LDBP_BWD_REGION", kBwdRegion);
+  h->streams = std::min(4, env_int("SSFM_LDBP_STREAMS", 0));
   if (!pow2(h->fwd_tile) || !pow2(h->bwd_region) || h->bwd_region < 256) {
     delete h;
     return api_fail(SSFM_EINVAL, "ldbp tile overrides must be powers of two (region >= 256)");
@@ -337,6 +395,11 @@ int ssfm_ldbp_destroy(ssfm_ldbp_t h) {
   ssfm::DeviceGuard guard(h->device);
   if (h->ws) (void)hipFree(h->ws);
   if (h->taps15) (void)hipFree(h->taps15);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  for (int k = 0; k < 3; ++k) {
+    if (h->join_ev[k]) (void)hipEventDestroy(h->join_ev[k]);
+    if (h->worker[k]) (void)hipStreamDestroy(h->worker[k]);
+  }
   delete h;
   return SSFM_OK;
 }
@@ -369,8 +432,11 @@ int ssfm_ldbp_forward(ssfm_ldbp_t h, const void* field_in, void* field_out, cons
   if (rc != SSFM_OK) return rc;
   hipError_t e = L::launch_pad_taps((const cd*)taps, h->d.n_steps, h->d.n_taps, h->taps15, st);
   if (e != hipSuccess) return api_fail_hip(e, "ldbp tap padding launch");
-  return run_forward(h, (const float2*)field_in, (float2*)field_out, xi, batch, (float2*)checkpoints,
-                     (float2*)h->ws, st);
+  return run_halves(h, batch, h->fwd_geom(h->fwd_chunk()).tiles, false, st,
+                    [&](int64_t b0, int64_t count, hipStream_t s) {
+                      return run_forward(h, (const float2*)field_in, (float2*)field_out, xi, batch,
+                                         b0, count, (float2*)checkpoints, (float2*)h->ws, s);
+                    });
 }
 
 int ssfm_ldbp_loss(ssfm_ldbp_t h, const void* field_out, const void* symbols, const double* mf,
@@ -473,28 +539,36 @@ int ssfm_ldbp_backward(ssfm_ldbp_t h, const void* field_in, const void* field_ou
     cur = 1;
   }
   const float2* ck = (const float2*)checkpoints;
-  for (int s = spans - 1; s >= 0; --s) {
-    L::BwdArgs a{};
-    a.x0 = s == 0 ? (const float2*)field_in : ck + (int64_t)(s - 1) * elems;
-    a.xs = s == spans - 1 ? (const float2*)field_out : ck + (int64_t)s * elems;
-    a.g_in = bufs[cur];
-    a.g_out = bufs[cur ^ 1];
-    a.taps15 = h->taps15;
-    a.xi = xi;
-    a.partial = partial;
-    a.n = h->d.n_samples;
-    a.batch = batch;
-    a.k0 = s * S;
-    a.s_steps = S;
-    a.w = g.w;
-    a.halo = g.halo;
-    a.region = g.region;
-    a.ls = g.ls;
-    a.tiles = g.tiles;
-    e = L::launch_bwd(h->d.n_pol, a, g.threads, g.lds, st);
-    if (e != hipSuccess) return api_fail_hip(e, "ldbp backward launch");
-    cur ^= 1;
-  }
+  const int cur0 = cur;
+  rc = run_halves(h, batch, g.tiles, true, st, [&](int64_t b0, int64_t count, hipStream_t hs) {
+    int c = cur0;
+    for (int s = spans - 1; s >= 0; --s) {
+      L::BwdArgs a{};
+      a.x0 = s == 0 ? (const float2*)field_in : ck + (int64_t)(s - 1) * elems;
+      a.xs = s == spans - 1 ? (const float2*)field_out : ck + (int64_t)s * elems;
+      a.g_in = bufs[c];
+      a.g_out = bufs[c ^ 1];
+      a.taps15 = h->taps15;
+      a.xi = xi;
+      a.partial = partial;
+      a.n = h->d.n_samples;
+      a.batch = batch;
+      a.b0 = b0;
+      a.count = count;
+      a.k0 = s * S;
+      a.s_steps = S;
+      a.w = g.w;
+      a.halo = g.halo;
+      a.region = g.region;
+      a.ls = g.ls;
+      a.tiles = g.tiles;
+      const hipError_t el = L::launch_bwd(h->d.n_pol, a, g.threads, g.lds, hs);
+      if (el != hipSuccess) return api_fail_hip(el, "ldbp backward launch");
+      c ^= 1;
+    }
+    return SSFM_OK;
+  });
+  if (rc != SSFM_OK) return rc;
   e = L::launch_reduce(partial, (int)nblk, h->d.n_steps, h->d.n_taps, (cd*)grad_taps, grad_xi, st);
   if (e != hipSuccess) return api_fail_hip(e, "ldbp gradient reduction launch");
   return SSFM_OK;

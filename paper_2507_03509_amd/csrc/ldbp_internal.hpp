@@ -33,7 +33,8 @@ struct FwdArgs {
   float2* ckpt;       // NULL, or span-start states [K/S - 1][batch][P][n]
   const cd* taps15;   // [K][15], centred and zero-padded
   const double* xi;   // [K]
-  int64_t n, batch;
+  int64_t n, batch;   // batch: the call's realisations (array strides)
+  int64_t b0, count;  // this launch's realisations [b0, b0 + count)
   int k0, k1, spans_steps;
   int w, halo, region, ls, tiles;  // ls: LDS stride of one polarisation
 };
@@ -47,7 +48,8 @@ struct BwdArgs {
   const cd* taps15;
   const double* xi;
   double* partial;     // [K][blocks][NRED], blocks = batch * tiles
-  int64_t n, batch;
+  int64_t n, batch;    // batch: the call's realisations (array strides)
+  int64_t b0, count;   // this launch's realisations [b0, b0 + count)
   int k0, s_steps;
   int w, halo, region, ls, tiles;
 };

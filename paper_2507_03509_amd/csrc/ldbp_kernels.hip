@@ -187,7 +187,7 @@ __global__ __launch_bounds__(512) void ldbp_fwd(FwdArgs a, const cd* __restrict_
   extern __shared__ __align__(16) unsigned char smem_f[];
   cd* st = reinterpret_cast<cd*>(smem_f);  // [P][ls]
   const int tid = threadIdx.x;
-  const int64_t b = blockIdx.x / a.tiles;
+  const int64_t b = a.b0 + blockIdx.x / a.tiles;  // realisation
   const int tile = (int)(blockIdx.x % a.tiles);
   const int64_t n0 = (int64_t)tile * a.w - a.halo;
   const int64_t nm = a.n - 1;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
   float2* G = xs_lds + a.s_steps * plane;
   double* red = reinterpret_cast<double*>(G + plane);
   const int tid = threadIdx.x;
-  const int64_t b = blockIdx.x / a.tiles;
+  const int64_t b = a.b0 + blockIdx.x / a.tiles;  // realisation
   const int tile = (int)(blockIdx.x % a.tiles);
   const int64_t n0 = (int64_t)tile * a.w - a.halo;
   const int64_t nm = a.n - 1;
@@ -426,7 +426,9 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
     }
     __syncthreads();
     // the tap gradient first: nothing else is live in the registers then
-    double* part = a.partial + ((int64_t)k * gridDim.x + blockIdx.x) * NRED;
+    // the partials of workgroup (b, tile) of the whole call, whichever
+    // launch ran it: [k][b tiles + tile]
+    double* part = a.partial + ((int64_t)k * a.batch * a.tiles + a.b0 * a.tiles + blockIdx.x) * NRED;
     tap_gradient<P>(G, X, a.ls, a.halo, wt, part);
     // FIR pullback at the lane's samples: gx[m] = sum_t conj(h[t]) gy[m - c + t]
     if (active) {
@@ -561,7 +563,15 @@ __global__ __launch_bounds__(256) void ldbp_loss_total(const double* __restrict_
   if (threadIdx.x == 0) *loss = (red[0] + red[1] + red[2] + red[3]) * inv_count;
 }
 
-// grad[n] = sum_m mf[sps m - n + R] ubar[m] over the symbols within R of n
+// grad[n] = sum_m mf[sps m - n + R] ubar[m] over the symbols within R of n.
+// For a sample n the taps that meet a symbol are k = k0 + sps j (k0 the
+// least k >= 0 with sps | n + k - R), meeting symbols m0(n) + j in order, so
+// the B samples n, n + sps, .., n + (B - 1) sps of one lane share k0 and see
+// the same symbols shifted by one: the lane streams its symbols through a B
+// value window in registers (one LDS read per tap for B outputs) and sums
+// each output over increasing m, as the direct sum does.  Lanes: sps phases
+// x (ns / sps) / B groups of B consecutive samples of one phase.
+template <int B>
 __global__ __launch_bounds__(256) void ldbp_mf_adjoint(MfAdjArgs a) {
   extern __shared__ __align__(16) unsigned char smem_m[];
   double* g = reinterpret_cast<double*>(smem_m);            // 2R + 1 taps
@@ -579,29 +589,60 @@ __global__ __launch_bounds__(256) void ldbp_mf_adjoint(MfAdjArgs a) {
   for (int i = threadIdx.x; i <= 2 * a.mf_half; i += blockDim.x) g[i] = a.mf[i];
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) us[i] = ur[(mlo + i) & mm];
   __syncthreads();
-  for (int q = threadIdx.x; q < a.ns; q += blockDim.x) {
-    // local coordinates: sample q of the tile is n = nb + q; symbol index
-    // m - mlo = i, tap index sps (i + mlo) - n + R = sps i + off
-    const int off = (int)(a.sps * mlo - nb) - q + a.mf_half;
-    // i with 0 <= sps i + off <= 2R
-    const int lo = off >= 0 ? 0 : (-off + a.sps - 1) / a.sps;
-    const int hi = (2 * a.mf_half - off) / a.sps;
-    cd acc{0.0, 0.0};
-    for (int i = lo; i <= hi; ++i) {
-      const double gj = g[a.sps * i + off];
-      const cd u = us[i];
-      acc.re = fma(gj, u.re, acc.re);
-      acc.im = fma(gj, u.im, acc.im);
-    }
-    store_c64(a.grad + row * a.n + nb + q, acc);
+  const int groups = a.ns / a.sps / B;  // lanes per phase
+  const int t = threadIdx.x;
+  if (t >= a.sps * groups) return;
+  const int rho = t / groups;
+  const int64_t n0 = nb + rho + (int64_t)a.sps * ((t % groups) * B);
+  const int k0 = (int)(((a.mf_half - n0) % a.sps + a.sps) % a.sps);
+  const int J = k0 <= 2 * a.mf_half ? (2 * a.mf_half - k0) / a.sps + 1 : 0;
+  // symbol of tap k0 for sample n0, relative to the staged range
+  const cd* uw = us + ((n0 + k0 - a.mf_half) / a.sps - mlo);
+  const int last = J + B - 2;  // the window's last symbol index
+  cd acc[B], w[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    acc[b] = cd{0.0, 0.0};
+    w[b] = cd{0.0, 0.0};
+    if (J > 0 && b <= last) w[b] = uw[b];
   }
+  // w[(s + b) % B] holds uw[j + s + b] at step j + s (j a multiple of B)
+  int j = 0;
+  for (; j + B <= J; j += B) {
+#pragma unroll
+    for (int s2 = 0; s2 < B; ++s2) {
+      const double gj = g[k0 + a.sps * (j + s2)];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const cd u = w[(s2 + b) % B];
+        acc[b].re = fma(gj, u.re, acc[b].re);
+        acc[b].im = fma(gj, u.im, acc[b].im);
+      }
+      if (j + s2 + B <= last) w[s2] = uw[j + s2 + B];
+    }
+  }
+#pragma unroll
+  for (int s2 = 0; s2 < B; ++s2) {
+    if (j + s2 < J) {
+      const double gj = g[k0 + a.sps * (j + s2)];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const cd u = w[(s2 + b) % B];
+        acc[b].re = fma(gj, u.re, acc[b].re);
+        acc[b].im = fma(gj, u.im, acc[b].im);
+      }
+      if (j + s2 + B <= last) w[s2] = uw[j + s2 + B];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < B; ++b) store_c64(a.grad + row * a.n + n0 + (int64_t)a.sps * b, acc[b]);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_fwd(int n_pol, const FwdArgs& a, int threads, size_t lds, hipStream_t st) {
-  const unsigned blocks = (unsigned)(a.batch * a.tiles);
+  const unsigned blocks = (unsigned)(a.count * a.tiles);
   if (n_pol == 1)
     hipLaunchKernelGGL(ldbp_fwd<1>, dim3(blocks), dim3(threads), lds, st, a, a.taps15, a.xi);
   else
@@ -610,7 +651,7 @@ hipError_t launch_fwd(int n_pol, const FwdArgs& a, int threads, size_t lds, hipS
 }
 
 hipError_t launch_bwd(int n_pol, const BwdArgs& a, int threads, size_t lds, hipStream_t st) {
-  const unsigned blocks = (unsigned)(a.batch * a.tiles);
+  const unsigned blocks = (unsigned)(a.count * a.tiles);
   if (n_pol == 1)
     hipLaunchKernelGGL(ldbp_bwd<1>, dim3(blocks), dim3(threads), lds, st, a, a.taps15, a.xi);
   else
@@ -634,7 +675,14 @@ hipError_t launch_loss_total(const double* partial, int count, double inv_count,
 hipError_t launch_mf_adjoint(const MfAdjArgs& a, int64_t rows, hipStream_t st) {
   const size_t lds = (size_t)(2 * a.mf_half + 2) * sizeof(double) +
                      (size_t)((a.ns + 2 * a.mf_half) / a.sps + 3) * sizeof(cd);
-  hipLaunchKernelGGL(ldbp_mf_adjoint, dim3((unsigned)(rows * a.tiles)), dim3(256), lds, st, a);
+  // B samples per lane, ns / B <= 256 lanes; ns / sps (a power of two) a
+  // multiple of B
+  const int per_phase = a.ns / a.sps;
+  const int B = (a.ns >= 1024 && per_phase % 4 == 0) ? 4 : (a.ns >= 512 && per_phase % 2 == 0) ? 2 : 1;
+  const dim3 grid((unsigned)(rows * a.tiles)), block((unsigned)(a.ns / B));
+  if (B == 4) hipLaunchKernelGGL(ldbp_mf_adjoint<4>, grid, block, lds, st, a);
+  else if (B == 2) hipLaunchKernelGGL(ldbp_mf_adjoint<2>, grid, block, lds, st, a);
+  else hipLaunchKernelGGL(ldbp_mf_adjoint<1>, grid, block, lds, st, a);
   return hipGetLastError();
 }
 

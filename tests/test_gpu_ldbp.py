@@ -169,6 +169,30 @@ def test_backward_is_bitwise_reproducible(ldbp):
         assert torch.equal(a, c)
 
 
+@pytest.mark.parametrize("b", [2, 5])
+def test_two_streams_are_bitwise_identical(ldbp, monkeypatch, b):
+    # the batch's parts on the caller's stream and the handle's worker
+    # streams (SSFM_LDBP_STREAMS=2, 3) against one stream (=1): every workgroup
+    # computes what it computes in one launch, the gradient partials land in
+    # the same slots, so forward, checkpoints and gradients are the same bits
+    print(f"ldbp two streams b={b}", flush=True)
+    p, n, k, s, t = 2, 4096, 6, 2, 15
+    rng, x, taps, xi = problem(6, b, p, n, k, t)
+    gz = c64(rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape))
+    xd, td, xid = dev(x, torch.complex64), dev(taps, torch.complex128), dev(xi, torch.float64)
+    res = {}
+    for streams in ("1", "2", "3"):
+        monkeypatch.setenv("SSFM_LDBP_STREAMS", streams)
+        model = make_model(ldbp, b, p, n, k, s, t)
+        ck = model.new_checkpoints(b)
+        z = model.forward(xd, td, xid, ck)
+        res[streams] = (z, ck) + tuple(model.backward(xd, z, td, xid, ck, dev(gz, torch.complex64)))
+    torch.cuda.synchronize()
+    for k in ("2", "3"):
+        for a, c in zip(res["1"], res[k]):
+            assert torch.equal(a, c)
+
+
 def received(batch, seed):
     """Workload-5 inputs: transmitted fields and targets (generator), then
     the oracle's propagation over the 10 x 80 km link at 2 steps per span
