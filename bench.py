@@ -577,13 +577,13 @@ def main() -> int:
     torch.cuda.synchronize()
 
     # the library's default (documented with ssfm_plan_set_forward_streams):
-    # each chunk as two concurrent parts when each part holds >= 2048 column
+    # each chunk as two concurrent parts when each part holds >= 256 column
     # tiles
     sub_batches = 1
     if info["path"] == 2:
         chunk = info["chunk_realisations"] or batch
         chunk = -(-batch // -(-batch // chunk))
-        sub_batches = 2 if chunk * info["n2"] // info["columns_per_tile"] >= 4096 else 1
+        sub_batches = 2 if chunk * info["n2"] // info["columns_per_tile"] >= 512 else 1
     # ---- timed region: K calls as the library runs them ---------------------
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)

@@ -264,8 +264,8 @@ int ssfm_adjoint_noalloc(ssfm_plan_t plan, const void* field_in, void* grad,
  * back into it with events, so the call stays ordered on that stream.  Parts
  * on separate streams fill the tail of each pass with the other parts' work.
  *   0      the library's choice (the default): two parts when each still
- *          holds at least 2048 column tiles (batch * n2 / 8 >= 4096, e.g.
- *          >= 128 realisations of 2^16 samples), else one;
+ *          holds at least 256 column tiles (batch * n2 / 8 >= 512, e.g.
+ *          >= 16 realisations of 2^16 samples), else one;
  *   1..5   that many parts (at most one per realisation).
  * Realisation b keeps its noise key and every part runs the same per-tile
  * arithmetic, so results are the same bit for bit whatever the setting.

@@ -276,7 +276,7 @@ def test_large_nonlinear_phase(ssfm, n, n_pol):
 @pytest.mark.parametrize("n,batch,parts", [(1 << 16, 128, 2), (1 << 16, 129, 2), (1 << 14, 3, 2),
                                            (1 << 14, 7, 3), (1 << 14, 9, 5), (1 << 16, 130, 0)])
 def test_two_stream_split_is_bitwise(ssfm, n, batch, parts):
-    # parts = 0: the library's own choice (two parts at >= 128 realisations
+    # parts = 0: the library's own choice (two parts at >= 16 realisations
     # of 2^16 samples)
     print(f"case n={n} batch={batch} parts={parts}", flush=True)
     ln = link(2, n, spans=2, steps=3)
