@@ -397,12 +397,27 @@ __global__ __launch_bounds__(256) void ldbp_bwd(BwdArgs a, const cd* __restrict_
     // Kerr pullback at the lane's samples (z = output, g = its gradient)
     double xi_part = 0.0;
     cd gy[P][R];
+    // e^{-i phi} by the short series when every phase of the wave is within
+    // 1/32 (the common case), else per sample by the series or the reduced
+    // form: a sample's rotation depends on its own phase only
+    bool wide = false;
     if (active) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         double pw = norm2(z[0][r]);
         if constexpr (P == 2) pw = pw + norm2(z[1][r]);
-        const cd e = phasor64(-xi * pw);  // e^{-i phi}
+        wide |= !(fabs(xi * pw) <= kShortPhase);
+      }
+    }
+    const bool any_wide = __any(wide);
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double pw = norm2(z[0][r]);
+        if constexpr (P == 2) pw = pw + norm2(z[1][r]);
+        const double phi = -xi * pw;
+        const cd e = !any_wide ? phasor_short(phi)
+                               : (fabs(phi) <= kShortPhase ? phasor_short(phi) : phasor64(phi));
         double s = 0.0;
 #pragma unroll
         for (int p = 0; p < P; ++p) s = fma(g[p][r].im, z[p][r].re, fma(-g[p][r].re, z[p][r].im, s));
