@@ -149,19 +149,19 @@ int ensure_ws(ssfm_ldbp_s* h, size_t bytes, hipStream_t st) {
 }
 
 // part(b0, count, stream) over the realisations [0, batch) of a call: as one
-// part on st, or as two halves, [0, batch/2) on st and the rest on the
-// handle's worker stream, forked from st and joined back into it (also after
-// an error, so no work is left unordered).  A launch of `blocks` workgroups
-// per realisation ends in a partly filled round of workgroups; the other
-// half's launches fill it.  by_size: the halves run by default when each
-// still has 512 or more workgroups per launch (the backward: 1088
-// workgroups at two per CU, 2.1 rounds per launch; at 64 x 2 x 2^14 the
-// training step went from 1.00 to 0.87 ms), else only when the handle asks
-// (the forward: 1024 workgroups at three per CU measured 13 % slower as
-// halves; three or four parts were no faster than two).  The setting is the
-// number of parts (1..4) when the handle asks.  Every workgroup computes
-// what it computes in one launch over the batch, so the results are the
-// same bits.
+// part on st, or as consecutive parts of nearly equal size, the first on st
+// and the others on the handle's worker streams, forked from st and joined
+// back into it (also after an error, so no work is left unordered).  A
+// launch of `blocks` workgroups per realisation ends in a partly filled
+// round of workgroups; the other parts' launches fill it.  By default
+// (streams 0) two halves run when by_size is set and each half still has
+// 512 or more workgroups per launch (the backward: 1088 workgroups at two
+// per CU, 2.1 rounds per launch; at 64 x 2 x 2^14 the training step went
+// from 1.00 to 0.87 ms); the forward (1024 workgroups at three per CU,
+// measured 13 % slower as halves) runs as one part unless the handle asks.
+// streams 2..4: that many parts in both (three or four were no faster than
+// two).  Every workgroup computes what it computes in one launch over the
+// batch, so the results are the same bits.
 template <typename F>
 int run_halves(ssfm_ldbp_s* h, int64_t batch, int64_t blocks, bool by_size, hipStream_t st,
                F&& part) {
