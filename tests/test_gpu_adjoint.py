@@ -75,6 +75,26 @@ def test_adjoint_workload2_full_link(ssfm):
     assert err < 1e-5
 
 
+def test_adjoint_workload2_bench_configuration(ssfm):
+    # the benchmarked adjoint: 512 realisations without kept spans, the
+    # forward pass in two 256-realisation chunks, the reverse sweep in four
+    # chunks of 128, every chunk as two concurrent parts; sampled
+    # realisations on both sides of chunk and part boundaries against the
+    # oracle's adjoint, one by one
+    w = CONFIGS[2]
+    batch = 512
+    host = np.stack([make_field(w, seed=w.symbol_seed + i) for i in range(8)])
+    rng = np.random.default_rng(512)
+    gh = np.stack([dual_pol_field(rng, 2, w.link.n_samples, 2, 64e9, 0.1, 0.0) for _ in range(8)])
+    x = np.tile(host, (batch // 8, 1, 1))
+    g = np.tile(gh, (batch // 8, 1, 1))
+    got, _ = gpu_adjoint(ssfm, x, g, w.link, seed=w.ase_seed)
+    for r in (63, 64, 511):
+        print(f"workload2 adjoint batch 512: realisation {r}", flush=True)
+        want = oracle.adjoint(x[r], g[r], w.link, seed=w.ase_seed, realization=r)
+        check(got[r], want, 1e-5, what=f"realisation {r}")
+
+
 def test_autograd_mse_gradient(ssfm):
     n = 1 << 14
     ln = link(2, n, spans=2, steps=4)

@@ -215,6 +215,31 @@ def test_workload2_full(ssfm):
     print(f"workload2 rel_err={err:.3e}", flush=True)
 
 
+def test_workload2_bench_configuration(ssfm):
+    # the benchmarked call: 512 realisations (16 distinct fields tiled, noise
+    # keys distinct), run as two cache-sized chunks of 256, each as two
+    # concurrent parts; sampled realisations on both sides of every chunk
+    # and part boundary against the oracle, one by one
+    w = CONFIGS[2]
+    batch = 512
+    host = np.stack([make_field(w, seed=w.symbol_seed + i) for i in range(16)])
+    x = np.ascontiguousarray(np.tile(host, (batch // 16, 1, 1)), dtype=np.complex64)
+    plan = ssfm.Plan(w.link)
+    try:
+        info = plan.info
+        assert info["chunk_realisations"] == 256
+        t = torch.from_numpy(x).cuda()
+        plan.forward(t, seed=w.ase_seed)
+        torch.cuda.synchronize()
+        got = t.cpu().numpy()
+    finally:
+        plan.close()
+    for r in (0, 127, 128, 256, 511):
+        print(f"workload2 batch 512: realisation {r}", flush=True)
+        want = oracle.propagate(x[r].astype(np.complex128), w.link, seed=w.ase_seed, realization=r)
+        check(got[r].astype(np.complex128), want, TOL, what=f"realisation {r}")
+
+
 def test_workload3_two_spans(ssfm):
     # the full 20-span oracle run takes minutes; two spans (400 steps) here,
     # the full length against the stored sampled reference below
