@@ -173,10 +173,11 @@ def test_ase_draws_match_oracle(ssfm, n, n_pol):
 # span-granular resume and determinism
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [2048, 1 << 16])
-def test_span_resume_is_bitwise(ssfm, n):
+# batch 20 at 2^16: two concurrent parts (the library's default from 16)
+@pytest.mark.parametrize("n,batch", [(2048, 2), (1 << 16, 2), (1 << 16, 20)])
+def test_span_resume_is_bitwise(ssfm, n, batch):
     ln = link(2, n, spans=3, steps=4)
-    a0 = qam(2, n, seed=8, batch=2)
+    a0 = qam(2, n, seed=8, batch=batch)
     whole = run_gpu(ssfm, a0, ln, seed=3)
     t = torch.from_numpy(a0.astype(np.complex64)).cuda()
     plan = ssfm.Plan(ln)
