@@ -335,7 +335,8 @@ def ssfm_plan_set_state_memory(plan: int, nbytes: int) -> None:
 
 
 def ssfm_plan_set_forward_streams(plan: int, streams: int) -> None:
-    """Concurrent sub-batches of a four-step call: 0 or 1 (one stream), 2."""
+    """Concurrent parts of each chunk of a four-step call: 0 the library's
+    choice (two from 256 column tiles per part), 1..5 that many."""
     _check(load_library().ssfm_plan_set_forward_streams(plan, int(streams)),
            "ssfm_plan_set_forward_streams")
 
@@ -437,7 +438,8 @@ class Plan:
         return ssfm_plan_autotune(self.handle, batch, stream)
 
     def set_forward_streams(self, streams: int) -> None:
-        """Concurrent sub-batches of a four-step call: 0 or 1 (one stream), 2."""
+        """Concurrent parts of each chunk of a four-step call: 0 the
+        library's choice (two from 256 column tiles per part), 1..5 that many."""
         ssfm_plan_set_forward_streams(self.handle, streams)
 
     def set_state_memory(self, nbytes: int) -> None:
